@@ -1,0 +1,184 @@
+/*
+ * mpgemm.h -- C ABI of libmpgemm: multiple-precision (MP) binary floating-point
+ * matrix multiplication and LU decomposition on one AMD Instinct MI355X
+ * (gfx950) GPU.
+ *
+ * Method: Kouya, "Accelerated Multiple Precision Matrix Multiplication using
+ * Strassen's Algorithm and Winograd's Variant" (arXiv 1410.1599): C := AB for
+ * any m, l, n at a fixed binary precision with round-to-nearest after every
+ * scalar operation (Sections 1 and 3), by Simple (eq. (1)), Block (eq. (2)),
+ * Strassen (Section 2, P1..P7) or Winograd's variant (eqs. (winograd_mod1) to
+ * (winograd_mod3)), recursing to a cutoff n_min with odd sizes peeled or
+ * padded (Section 2, last paragraph); and the blocked LU of Section 4, whose
+ * trailing update A22 := A22 - L21 U12 forms the product with one of these
+ * algorithms (here with partial pivoting).
+ *
+ * ------------------------------------------------------------------ numbers
+ * prec p is 128, 256 or 512 bits; L = p / 32.  A value is
+ *     (-1)^s * M * 2^(e - p),   2^(p-1) <= M < 2^p   (M normalised),
+ * or zero (M = 0, e = 0, s = 0; there is one zero, +0).  Every operation
+ * rounds its exact result to the nearest p-bit value, ties to the even
+ * mantissa.  Precondition: |e| < 2^29 for every input (not checked).
+ *
+ * ------------------------------------------------------------------ matrices
+ * An r x c matrix is one device buffer of uint32 words in "plane" layout:
+ * element (i, j) has
+ *     limb k (k = 0 least significant) at  X[k * ps + i * ld + j],  k < L,
+ *     exponent e (int32 bits)          at  X[L * ps + i * ld + j],
+ *     sign s (0 or 1)                  at  X[(L + 1) * ps + i * ld + j],
+ * with leading dimension ld >= c and plane stride ps >= (r - 1) ld + c.  The
+ * buffer spans (L + 2) * ps words.  A sub-matrix is a pointer offset with the
+ * same ld and ps.  Limb-major planes make the reads of consecutive elements
+ * coalesce.
+ *
+ * ------------------------------------------------------------------ conventions
+ * Pointers are device pointers unless a parameter says "host".  The caller
+ * owns every matrix and pivot array.  The library owns only its workspace (one
+ * per stream, grown on demand, freed by mp_release_workspace) and cached
+ * launch plans.
+ *
+ * Work is enqueued on the stream last set by mp_set_stream on the calling
+ * thread (the null stream by default) and the call returns without waiting,
+ * except where stated.  Calls that share a stream are ordered; calls on
+ * different streams use different workspaces.
+ *
+ * Return codes: MP_OK (0) or a negative MP_E_* code.  A negative return means
+ * nothing was enqueued and nothing was written; mp_last_error() then gives a
+ * message (thread-local).  An asynchronous device fault of earlier work is
+ * reported as MP_E_DEVICE by the next call.
+ */
+#ifndef MPGEMM_H
+#define MPGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPGEMM_VERSION 1
+
+enum mp_algo {
+    MP_SIMPLE = 0,    /* eq. (1): c_ij = sum_k a_ik b_kj, k ascending from exact 0 */
+    MP_BLOCK = 1,     /* eq. (2): LDS-staged tiles, same per-element order as Simple (bit-identical) */
+    MP_STRASSEN = 2,  /* Section 2: P1..P7 and the C quadrants, recursing above the cutoff */
+    MP_WINOGRAD = 3   /* Section 2: Winograd's variant S1..S8, M1..M7, T1, T2 */
+};
+
+enum mp_policy {      /* odd dimensions above the cutoff (Section 2, last paragraph) */
+    MP_PEEL = 0,      /* peel the last row / column / inner index (default) */
+    MP_PAD = 1,       /* pad with an exact zero row / column */
+    MP_MIXED = 2      /* pad d = 3 mod 4, peel d = 1 mod 4 (reproduces Table 1) */
+};
+
+enum mp_leaf {        /* kernel for the products below the cutoff */
+    MP_LEAF_SIMPLE = 0,
+    MP_LEAF_BLOCK = 1
+};
+
+enum mp_status {
+    MP_OK = 0,
+    MP_E_ARG = -1,    /* bad size, stride, pointer or enum */
+    MP_E_PREC = -2,   /* prec not 128, 256 or 512 */
+    MP_E_ALIAS = -3,  /* output buffer overlaps an input buffer */
+    MP_E_NOMEM = -4,  /* device allocation failed */
+    MP_E_DEVICE = -5, /* HIP error (launch failure or earlier asynchronous fault) */
+    MP_E_RANGE = -6   /* a dimension above 2^31 - 1 */
+};
+
+/* Stream for later calls from this thread (a hipStream_t; NULL = null stream). */
+int mp_set_stream(void *hip_stream);
+
+/* Message of the last failed call on this thread (static storage, thread-local). */
+const char *mp_last_error(void);
+
+/* MPGEMM_VERSION of the built library. */
+int mp_version(void);
+
+/*
+ * Defaults used by mp_gemm: odd-size policy (enum mp_policy) and leaf kernel
+ * (enum mp_leaf).  Process-wide.  MP_E_ARG for an unknown value.
+ */
+int mp_set_policy(int odd_policy, int leaf);
+
+/*
+ * C := A B at precision prec (Section 2).  A is m x l, B is l x n, C is m x n,
+ * each in plane layout with its own ld and plane stride.  algo: enum mp_algo.
+ * cutoff: the recursion threshold n_min for MP_STRASSEN / MP_WINOGRAD (>= 1):
+ * a product recurses while min(m, l, n) > cutoff, and below it is Simple;
+ * ignored by MP_SIMPLE and MP_BLOCK.  Odd sizes follow mp_set_policy (PEEL by
+ * default).  Zero m or n is a no-op; zero l writes C = 0.  C must not overlap
+ * A or B (MP_E_ALIAS); A may alias B.  The result is bit-identical to the
+ * CPU oracle performing the same sequence of correctly rounded operations.
+ */
+int mp_gemm(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff,
+            const uint32_t *A, int64_t lda, int64_t psa,
+            const uint32_t *B, int64_t ldb, int64_t psb,
+            uint32_t *C, int64_t ldc, int64_t psc);
+
+/* mp_gemm with an explicit odd-size policy (enum mp_policy) and leaf kernel (enum mp_leaf). */
+int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, int policy, int leaf,
+               const uint32_t *A, int64_t lda, int64_t psa,
+               const uint32_t *B, int64_t ldb, int64_t psb,
+               uint32_t *C, int64_t ldc, int64_t psc);
+
+/*
+ * Elementwise C := A op B on m x n matrices, one rounding per element: the
+ * matrix additions and subtractions of Strassen's and Winograd's levels
+ * (Section 2), and products and true quotients for completeness.  C may alias
+ * A or B exactly (same pointer and strides: in-place update).
+ */
+int mp_add(int64_t m, int64_t n, int prec, const uint32_t *A, int64_t lda, int64_t psa,
+           const uint32_t *B, int64_t ldb, int64_t psb, uint32_t *C, int64_t ldc, int64_t psc);
+int mp_sub(int64_t m, int64_t n, int prec, const uint32_t *A, int64_t lda, int64_t psa,
+           const uint32_t *B, int64_t ldb, int64_t psb, uint32_t *C, int64_t ldc, int64_t psc);
+int mp_mul_ew(int64_t m, int64_t n, int prec, const uint32_t *A, int64_t lda, int64_t psa,
+              const uint32_t *B, int64_t ldb, int64_t psb, uint32_t *C, int64_t ldc, int64_t psc);
+/* B must have no zero entry (a zero divisor gives an unspecified value). */
+int mp_div_ew(int64_t m, int64_t n, int prec, const uint32_t *A, int64_t lda, int64_t psa,
+              const uint32_t *B, int64_t ldb, int64_t psb, uint32_t *C, int64_t ldc, int64_t psc);
+
+/*
+ * Host-only description of the plan mp_gemm would run for (m, l, n) with
+ * contiguous operands (ld = column count, ps = rows x cols): recursion depth,
+ * scalar MP multiplications and additions/subtractions (the Mul and Addsub
+ * counts of Section 2 / Table 1), workspace bytes and number of grouped
+ * launches.  Any output pointer may be NULL.  Needs no GPU.
+ */
+int mp_plan_info(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, int policy,
+                 int *depth, double *n_mul, double *n_addsub, int64_t *ws_bytes, int64_t *n_launches);
+
+/*
+ * LU decomposition with partial pivoting of the n x n matrix A in place
+ * (Section 4, blocked with panel width K, trailing update A22 := A22 - L21 U12
+ * with the product formed by `algo`; the paper's LU does not pivot, this one
+ * pivots by rows).  On return A holds U on and above the diagonal and the
+ * multipliers of the unit lower L below it.  piv (device, n int32) receives
+ * LAPACK getrf-style 0-based pivots: at step k rows k and piv[k] were swapped.
+ * *info (host) is 0, or k + 1 for the first column k whose pivot was exactly
+ * zero (the factorisation still completes).  Pivot = the first row index of
+ * the largest |a_ik|; multipliers are true quotients.  Synchronises the
+ * stream to read info.
+ * mp_lu uses panel 64, MP_WINOGRAD, cutoff 32 and the policy of mp_set_policy.
+ */
+int mp_lu(int64_t n, int prec, uint32_t *A, int64_t lda, int64_t psa, int32_t *piv, int32_t *info);
+int mp_lu_ex(int64_t n, int prec, uint32_t *A, int64_t lda, int64_t psa, int32_t *piv, int32_t *info,
+             int panel, int algo, int cutoff, int policy);
+
+/*
+ * Solve A x = b from the factors of mp_lu: the row swaps of piv in order,
+ * forward substitution with the unit lower factor, back substitution with the
+ * upper factor (true quotients by the diagonal).  b (n x 1, plane stride psb)
+ * is overwritten by x.  Asynchronous.
+ */
+int mp_lu_solve(int64_t n, int prec, const uint32_t *LU, int64_t lda, int64_t psa, const int32_t *piv,
+                uint32_t *b, int64_t psb);
+
+/* Free the workspaces and cached plans of the current device (synchronises the device). */
+int mp_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPGEMM_H */

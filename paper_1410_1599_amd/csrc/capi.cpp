@@ -1,0 +1,396 @@
+// capi.cpp -- the C ABI of libmpgemm (declared in include/mpgemm.h).
+//
+// Argument checking happens before anything is enqueued: a negative return
+// means nothing was launched and nothing was written.  Work is enqueued on the
+// calling thread's stream (mp_set_stream) and the calls return without
+// waiting, except mp_lu / mp_lu_ex, which return the LAPACK-style info.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "launch.hpp"
+#include "mpgemm_internal.hpp"
+#include "plan.hpp"
+
+namespace mpg {
+
+thread_local hipStream_t g_stream = nullptr;
+thread_local std::string g_err;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct DeviceState {
+    std::mutex mu;
+    std::unordered_map<PlanKey, std::unique_ptr<Plan>, PlanKeyHash> plans;
+    std::map<std::pair<hipStream_t, int>, DevBuf> ws;     // per stream and slot
+};
+
+std::mutex g_dev_mu;
+std::map<int, std::unique_ptr<DeviceState>> g_dev;
+
+DeviceState& dev_state()
+{
+    int d = 0;
+    (void)hipGetDevice(&d);
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    auto& p = g_dev[d];
+    if (!p) p.reset(new DeviceState());
+    return *p;
+}
+
+void free_plan_device(Plan& P)
+{
+    if (P.d_gemm) (void)hipFree(P.d_gemm);
+    if (P.d_node) (void)hipFree(P.d_node);
+    if (P.d_tiles) (void)hipFree(P.d_tiles);
+    P.d_gemm = nullptr;
+    P.d_node = nullptr;
+    P.d_tiles = nullptr;
+}
+
+template <class T>
+int upload(T** dst, const std::vector<T>& v)
+{
+    if (v.empty()) return MP_OK;
+    if (hipMalloc((void**)dst, sizeof(T) * v.size()) != hipSuccess) return set_err(MP_E_NOMEM, "hipMalloc of a plan failed");
+    if (hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return set_err(MP_E_DEVICE, "upload of a plan failed");
+    return MP_OK;
+}
+
+}  // namespace
+
+int set_err(int code, const char* msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int check_prec(int prec, int* L)
+{
+    if (prec != 128 && prec != 256 && prec != 512)
+        return set_err(MP_E_PREC, "prec must be 128, 256 or 512");
+    *L = prec / 32;
+    return MP_OK;
+}
+
+int check_mat(const char* name, const uint32_t* p, int64_t rows, int64_t cols, int64_t ld, int64_t ps)
+{
+    if (rows < 0 || cols < 0) return set_err(MP_E_ARG, "negative dimension");
+    if (rows > INT32_MAX || cols > INT32_MAX) return set_err(MP_E_RANGE, "dimension above 2^31 - 1");
+    if (rows == 0 || cols == 0) return MP_OK;
+    if (!p) {
+        g_err = std::string(name) + " is NULL";
+        return MP_E_ARG;
+    }
+    if (ld < cols) {
+        g_err = std::string(name) + ": leading dimension smaller than the column count";
+        return MP_E_ARG;
+    }
+    if (ps < (rows - 1) * ld + cols) {
+        g_err = std::string(name) + ": plane stride smaller than the matrix";
+        return MP_E_ARG;
+    }
+    return MP_OK;
+}
+
+bool overlaps(const uint32_t* a, int64_t psa, const uint32_t* b, int64_t psb, int L)
+{
+    const uintptr_t a0 = (uintptr_t)a, a1 = a0 + 4ull * (uint64_t)(L + 2) * (uint64_t)psa;
+    const uintptr_t b0 = (uintptr_t)b, b1 = b0 + 4ull * (uint64_t)(L + 2) * (uint64_t)psb;
+    return a0 < b1 && b0 < a1;
+}
+
+int device_check()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_err = std::string("device error: ") + hipGetErrorString(e);
+        return MP_E_DEVICE;
+    }
+    return MP_OK;
+}
+
+Plan* get_plan(const PlanKey& key, int* rc)
+{
+    DeviceState& S = dev_state();
+    std::lock_guard<std::mutex> g(S.mu);
+    auto it = S.plans.find(key);
+    if (it != S.plans.end()) return it->second.get();
+    std::unique_ptr<Plan> P(new Plan());
+    build_plan(*P, key);
+    const char* why = nullptr;
+    if (!validate_plan(*P, &why)) {
+        *rc = set_err(MP_E_ARG, why);      // a planner defect: refuse rather than launch
+        return nullptr;
+    }
+    if ((*rc = upload(&P->d_gemm, P->gemm)) || (*rc = upload(&P->d_node, P->node)) ||
+        (*rc = upload(&P->d_tiles, P->tiles))) {
+        free_plan_device(*P);
+        return nullptr;
+    }
+    Plan* raw = P.get();
+    S.plans[key] = std::move(P);
+    return raw;
+}
+
+uint32_t* workspace(size_t words, hipStream_t s, int slot, int* rc)
+{
+    *rc = MP_OK;
+    if (words == 0) return nullptr;
+    DeviceState& S = dev_state();
+    std::lock_guard<std::mutex> g(S.mu);
+    DevBuf& b = S.ws[std::make_pair(s, slot)];
+    const size_t bytes = words * 4;
+    if (b.bytes < bytes) {
+        if (b.p) {
+            (void)hipStreamSynchronize(s);    // earlier work on this stream may still use it
+            (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *rc = set_err(MP_E_NOMEM, "workspace allocation failed");
+            return nullptr;
+        }
+        b.bytes = bytes;
+    }
+    return (uint32_t*)b.p;
+}
+
+int64_t grid_for(int64_t ntiles)
+{
+    return ntiles < (int64_t(1) << 30) ? ntiles : (int64_t(1) << 30);
+}
+
+int run_plan(const Plan& P, Bases bs, hipStream_t s)
+{
+    int rc = MP_OK;
+    bs.p[BASE_WS] = workspace((size_t)P.ws_words, s, WS_PLAN, &rc);
+    if (rc) return rc;
+    // the tile map holds indices into the plan's whole task arrays
+    for (const Step& st : P.steps) {
+        hipError_t e;
+        if (st.kind == 0)
+            e = launch_gemm(P.key.L, st.op, P.d_gemm, P.d_tiles + st.tile0, st.ntiles, bs,
+                            grid_for(st.ntiles), s);
+        else
+            e = launch_node(P.key.L, st.op, P.d_node, P.d_tiles + st.tile0, st.ntiles, bs,
+                            grid_for(st.ntiles), s);
+        if (e != hipSuccess) {
+            g_err = std::string("launch failed: ") + hipGetErrorString(e);
+            return MP_E_DEVICE;
+        }
+    }
+    return MP_OK;
+}
+
+int gemm_internal(int64_t m, int64_t l, int64_t n, int L, int algo, int cutoff, int policy, int leaf,
+                  const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
+                  uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s)
+{
+    if (m == 0 || n == 0) return MP_OK;
+    PlanKey key{m, l, n, L, algo, cutoff, policy, algo == ALGO_BLOCK ? 1 : leaf, lda, psa, ldb, psb, ldc, psc};
+    if (algo == ALGO_SIMPLE || algo == ALGO_BLOCK) key.cutoff = 0, key.policy = 0;
+    int rc = MP_OK;
+    Plan* P = get_plan(key, &rc);
+    if (!P) return rc ? rc : MP_E_NOMEM;
+    Bases bs{};
+    bs.p[BASE_A] = const_cast<uint32_t*>(A);
+    bs.p[BASE_B] = const_cast<uint32_t*>(B);
+    bs.p[BASE_C] = C;
+    return run_plan(*P, bs, s);
+}
+
+int ew_internal(int op, int64_t m, int64_t n, int L, const uint32_t* A, int64_t lda, int64_t psa,
+                const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s)
+{
+    if (m == 0 || n == 0) return MP_OK;
+    int rc;
+    // a one-task plan, cached like a product plan (algo field = 100 + op)
+    PlanKey key{m, 0, n, L, 100 + op, 0, 0, 0, lda, psa, ldb, psb, ldc, psc};
+    DeviceState& S = dev_state();
+    Plan* P = nullptr;
+    {
+        std::lock_guard<std::mutex> g(S.mu);
+        auto it = S.plans.find(key);
+        if (it != S.plans.end()) P = it->second.get();
+    }
+    if (!P) {
+        std::unique_ptr<Plan> np(new Plan());
+        np->key = key;
+        NodeTask t{};
+        t.in[0] = MatRef{BASE_A, 0, 0, lda, psa};
+        t.in[1] = MatRef{BASE_B, 0, 0, ldb, psb};
+        t.out[0] = MatRef{BASE_C, 0, 0, ldc, psc};
+        t.rows = (int32_t)m;
+        t.cols = (int32_t)n;
+        t.tile0 = 0;
+        np->node.push_back(t);
+        const int64_t nt = (m * n + NODE_TILE - 1) / NODE_TILE;
+        np->tiles.assign((size_t)nt, 0);
+        np->steps.push_back(Step{1, op, 0, 1, 0, nt});
+        if ((rc = upload(&np->d_node, np->node)) || (rc = upload(&np->d_tiles, np->tiles))) {
+            free_plan_device(*np);
+            return rc;
+        }
+        std::lock_guard<std::mutex> g(S.mu);
+        P = np.get();
+        S.plans[key] = std::move(np);
+    }
+    Bases bs{};
+    bs.p[BASE_A] = const_cast<uint32_t*>(A);
+    bs.p[BASE_B] = const_cast<uint32_t*>(B);
+    bs.p[BASE_C] = C;
+    return run_plan(*P, bs, s);
+}
+
+int g_leaf = LEAF_SIMPLE;
+int g_policy = POLICY_PEEL;
+
+}  // namespace mpg
+
+using namespace mpg;
+
+extern "C" {
+
+int mp_set_stream(void* stream)
+{
+    g_stream = (hipStream_t)stream;
+    return MP_OK;
+}
+
+const char* mp_last_error(void)
+{
+    return g_err.c_str();
+}
+
+int mp_version(void)
+{
+    return MPGEMM_VERSION;
+}
+
+int mp_set_policy(int odd_policy, int leaf)
+{
+    if (odd_policy < POLICY_PEEL || odd_policy > POLICY_MIXED) return set_err(MP_E_ARG, "unknown odd-size policy");
+    if (leaf != LEAF_SIMPLE && leaf != LEAF_BLOCK) return set_err(MP_E_ARG, "unknown leaf kernel");
+    g_policy = odd_policy;
+    g_leaf = leaf;
+    return MP_OK;
+}
+
+int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, int policy, int leaf,
+               const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
+               uint32_t* C, int64_t ldc, int64_t psc)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if (algo < ALGO_SIMPLE || algo > ALGO_WINOGRAD) return set_err(MP_E_ARG, "unknown algorithm");
+    if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
+    if (policy < POLICY_PEEL || policy > POLICY_MIXED) return set_err(MP_E_ARG, "unknown odd-size policy");
+    if (leaf != LEAF_SIMPLE && leaf != LEAF_BLOCK) return set_err(MP_E_ARG, "unknown leaf kernel");
+    if (m < 0 || l < 0 || n < 0) return set_err(MP_E_ARG, "negative dimension");
+    if ((rc = check_mat("A", A, m, l, lda, psa)) || (rc = check_mat("B", B, l, n, ldb, psb)) ||
+        (rc = check_mat("C", C, m, n, ldc, psc)))
+        return rc;
+    if (m == 0 || n == 0) return MP_OK;
+    if (l > 0 && (overlaps(C, psc, A, psa, L) || overlaps(C, psc, B, psb, L)))
+        return set_err(MP_E_ALIAS, "C overlaps A or B");
+    if ((rc = device_check())) return rc;
+    rc = gemm_internal(m, l, n, L, algo, cutoff, policy, leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, g_stream);
+    if (rc) return rc;
+    return device_check();
+}
+
+int mp_gemm(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, const uint32_t* A, int64_t lda,
+            int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc)
+{
+    return mp_gemm_ex(m, l, n, prec, algo, cutoff, g_policy, g_leaf, A, lda, psa, B, ldb, psb, C, ldc, psc);
+}
+
+static int elementwise(int op, int64_t m, int64_t n, int prec, const uint32_t* A, int64_t lda, int64_t psa,
+                       const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if ((rc = check_mat("A", A, m, n, lda, psa)) || (rc = check_mat("B", B, m, n, ldb, psb)) ||
+        (rc = check_mat("C", C, m, n, ldc, psc)))
+        return rc;
+    if (m == 0 || n == 0) return MP_OK;
+    if ((rc = device_check())) return rc;
+    if ((rc = ew_internal(op, m, n, L, A, lda, psa, B, ldb, psb, C, ldc, psc, g_stream))) return rc;
+    return device_check();
+}
+
+int mp_add(int64_t m, int64_t n, int prec, const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B,
+           int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc)
+{
+    return elementwise(OP_ADD, m, n, prec, A, lda, psa, B, ldb, psb, C, ldc, psc);
+}
+
+int mp_sub(int64_t m, int64_t n, int prec, const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B,
+           int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc)
+{
+    return elementwise(OP_SUB, m, n, prec, A, lda, psa, B, ldb, psb, C, ldc, psc);
+}
+
+int mp_mul_ew(int64_t m, int64_t n, int prec, const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B,
+              int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc)
+{
+    return elementwise(OP_MUL, m, n, prec, A, lda, psa, B, ldb, psb, C, ldc, psc);
+}
+
+int mp_div_ew(int64_t m, int64_t n, int prec, const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B,
+              int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc)
+{
+    return elementwise(OP_DIV, m, n, prec, A, lda, psa, B, ldb, psb, C, ldc, psc);
+}
+
+int mp_plan_info(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, int policy, int* depth,
+                 double* n_mul, double* n_addsub, int64_t* ws_bytes, int64_t* n_launches)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if (algo < ALGO_SIMPLE || algo > ALGO_WINOGRAD) return set_err(MP_E_ARG, "unknown algorithm");
+    if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
+    if (policy < POLICY_PEEL || policy > POLICY_MIXED) return set_err(MP_E_ARG, "unknown odd-size policy");
+    if (m < 0 || l < 0 || n < 0) return set_err(MP_E_ARG, "negative dimension");
+    Plan P;
+    PlanKey key{m, l, n, L, algo, cutoff, policy, 0, l, m * l, n, l * n, n, m * n};
+    build_plan(P, key);
+    const char* why = nullptr;
+    if (!validate_plan(P, &why)) return set_err(MP_E_ARG, why);
+    if (depth) *depth = P.depth;
+    if (n_mul) *n_mul = P.n_mul;
+    if (n_addsub) *n_addsub = P.n_addsub;
+    if (ws_bytes) *ws_bytes = P.ws_words * 4;
+    if (n_launches) *n_launches = (int64_t)P.steps.size();
+    return MP_OK;
+}
+
+int mp_release_workspace(void)
+{
+    DeviceState& S = dev_state();
+    std::lock_guard<std::mutex> g(S.mu);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : S.ws)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    S.ws.clear();
+    for (auto& kv : S.plans) free_plan_device(*kv.second);
+    S.plans.clear();
+    return MP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+// gemm_kernels.hip -- leaf products and per-node elementwise passes.
+//
+// Leaf product (Section 2, eq. (1)): every output element is owned by one
+// lane, which runs c := add_rn(c, mul_rn(a_ik, b_kj)) for k ascending from an
+// exact zero.  A workgroup owns TM rows x 64 columns of one product: each
+// wave one row, each lane one column, so a wave reads one A element per k
+// (the same address in every lane) and 64 consecutive B elements.
+//
+// Block (eq. (2)) stages TK x 64 tiles of B and TM x TK tiles of A in LDS and
+// runs the same per-element k order, so it is bit-identical to Simple.
+//
+// Every launch is grouped: a list of GemmTasks (up to the 7^d leaves of a
+// Strassen/Winograd plan plus its peel products) is cut into tiles, and
+// tile_task maps a tile to its task.  The grid may be smaller than the tile
+// count (persistent mode): workgroups stride over the tiles.
+#include "launch.hpp"
+#include "mp_arith.hpp"
+
+namespace mpg {
+
+template <int L>
+__device__ __forceinline__ const uint32_t* ref_ptr(const Bases& b, const MatRef& r)
+{
+    return b.p[r.base] + r.off;
+}
+
+// ------------------------------------------------------------------ Simple
+
+template <int L, int TM>
+__global__ void __launch_bounds__(64 * TM)
+k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
+{
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const GemmTask T = tasks[tile_task[t]];
+        const int64_t lt = t - T.tile0;
+        // a tile is (64 TM / 2^tcl) rows x 2^tcl columns, lanes along a row
+        const int tc = 1 << T.tcl;
+        const int tr = (64 * TM) >> T.tcl;
+        const int tn = (T.n + tc - 1) >> T.tcl;
+        const int64_t i = (lt / tn) * tr + (threadIdx.x >> T.tcl);
+        const int64_t j = (lt % tn) * tc + (threadIdx.x & (tc - 1));
+        if (i >= T.m || j >= T.n) continue;
+        const uint32_t* A = ref_ptr<L>(bs, T.A) + i * T.A.ld;
+        const uint32_t* B = ref_ptr<L>(bs, T.B) + j;
+        uint32_t* C = bs.p[T.C.base] + T.C.off + i * T.C.ld + j;
+        MP<L> c = T.accum ? load<L>(C, T.C.ps, 0) : mp_zero<L>();
+        for (int k = 0; k < T.l; k++) {
+            const MP<L> a = load<L>(A, T.A.ps, k);
+            const MP<L> b = load<L>(B, T.B.ps, (int64_t)k * T.B.ld);
+            c = add_rn<L>(c, mul_rn<L>(a, b));
+        }
+        store<L>(C, T.C.ps, 0, c);
+    }
+}
+
+// ------------------------------------------------------------------ Block (LDS tiles)
+
+template <int L, int TM, int TK>
+__global__ void __launch_bounds__(64 * TM)
+k_gemm_block(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
+{
+    constexpr int W = L + 2;                  // words per element
+    __shared__ uint32_t sB[TK][W][64];        // B tile, limb-major so lanes read consecutive words
+    __shared__ uint32_t sA[TM][TK][W];        // A tile, one row per wave (broadcast reads)
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int nt = 64 * TM;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const GemmTask T = tasks[tile_task[t]];
+        const int64_t lt = t - T.tile0;
+        const int tn = (T.n + 63) >> 6;
+        const int64_t i0 = (lt / tn) * TM;
+        const int64_t j0 = (lt % tn) * 64;
+        const int64_t i = i0 + w, j = j0 + lane;
+        const bool live = (i < T.m) && (j < T.n);
+        const uint32_t* A = ref_ptr<L>(bs, T.A);
+        const uint32_t* B = ref_ptr<L>(bs, T.B);
+        uint32_t* C = bs.p[T.C.base] + T.C.off;
+        MP<L> c = (T.accum && live) ? load<L>(C + i * T.C.ld + j, T.C.ps, 0) : mp_zero<L>();
+        for (int k0 = 0; k0 < T.l; k0 += TK) {
+            __syncthreads();
+            // stage B[k0 .. k0+TK) x [j0 .. j0+64): zero outside the product
+            for (int e = threadIdx.x; e < TK * 64 * W; e += nt) {
+                const int col = e & 63;
+                const int rest = e >> 6;
+                const int word = rest % W;
+                const int kk = rest / W;
+                const int64_t k = k0 + kk, jj = j0 + col;
+                uint32_t v = 0;
+                if (k < T.l && jj < T.n) v = B[word * T.B.ps + k * T.B.ld + jj];
+                sB[kk][word][col] = v;
+            }
+            for (int e = threadIdx.x; e < TM * TK * W; e += nt) {
+                const int word = e % W;
+                const int kk = (e / W) % TK;
+                const int r = e / (W * TK);
+                const int64_t k = k0 + kk, ii = i0 + r;
+                uint32_t v = 0;
+                if (k < T.l && ii < T.m) v = A[word * T.A.ps + ii * T.A.ld + k];
+                sA[r][kk][word] = v;
+            }
+            __syncthreads();
+            const int kn = (T.l - k0) < TK ? (T.l - k0) : TK;
+            for (int kk = 0; kk < kn; kk++) {
+                MP<L> a, b;
+#pragma unroll
+                for (int q = 0; q < L; q++) {
+                    a.m[q] = sA[w][kk][q];
+                    b.m[q] = sB[kk][q][lane];
+                }
+                a.e = (int32_t)sA[w][kk][L];
+                a.s = sA[w][kk][L + 1];
+                b.e = (int32_t)sB[kk][L][lane];
+                b.s = sB[kk][L + 1][lane];
+                c = add_rn<L>(c, mul_rn<L>(a, b));
+            }
+        }
+        if (live) store<L>(C + i * T.C.ld + j, T.C.ps, 0, c);
+    }
+}
+
+// ------------------------------------------------------------------ node passes
+
+template <int L>
+__device__ __forceinline__ MP<L> ld(const Bases& bs, const MatRef& r, int64_t i, int64_t j)
+{
+    return load<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j);
+}
+
+template <int L>
+__device__ __forceinline__ void st(const Bases& bs, const MatRef& r, int64_t i, int64_t j, const MP<L>& v)
+{
+    store<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j, v);
+}
+
+template <int L, int OP>
+__global__ void __launch_bounds__(NODE_TILE)
+k_node(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
+{
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const NodeTask& T = tasks[tile_task[t]];
+        const int64_t e = (t - T.tile0) * NODE_TILE + threadIdx.x;
+        const int64_t total = (int64_t)T.rows * T.cols;
+        if (e >= total) continue;
+        const int64_t i = e / T.cols, j = e % T.cols;
+        if constexpr (OP == OP_ADD) {
+            st<L>(bs, T.out[0], i, j, add_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
+        } else if constexpr (OP == OP_SUB) {
+            st<L>(bs, T.out[0], i, j, sub_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
+        } else if constexpr (OP == OP_MUL) {
+            st<L>(bs, T.out[0], i, j, mul_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
+        } else if constexpr (OP == OP_DIV) {
+            st<L>(bs, T.out[0], i, j, div_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
+        } else if constexpr (OP == OP_COPY) {
+            st<L>(bs, T.out[0], i, j, ld<L>(bs, T.in[0], i, j));
+        } else if constexpr (OP == OP_PADCOPY) {
+            const bool in = i < T.aux0 && j < T.aux1;
+            st<L>(bs, T.out[0], i, j, in ? ld<L>(bs, T.in[0], i, j) : mp_zero<L>());
+        } else if constexpr (OP == OP_WINO_A) {
+            // S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2
+            const MP<L> a11 = ld<L>(bs, T.in[0], i, j), a12 = ld<L>(bs, T.in[1], i, j);
+            const MP<L> a21 = ld<L>(bs, T.in[2], i, j), a22 = ld<L>(bs, T.in[3], i, j);
+            const MP<L> s1 = add_rn<L>(a21, a22);
+            const MP<L> s2 = sub_rn<L>(s1, a11);
+            st<L>(bs, T.out[0], i, j, s1);
+            st<L>(bs, T.out[1], i, j, s2);
+            st<L>(bs, T.out[2], i, j, sub_rn<L>(a11, a21));
+            st<L>(bs, T.out[3], i, j, sub_rn<L>(a12, s2));
+        } else if constexpr (OP == OP_WINO_B) {
+            // S5 = B12 - B11, S6 = B22 - S5, S7 = B22 - B12, S8 = S6 - B21
+            const MP<L> b11 = ld<L>(bs, T.in[0], i, j), b12 = ld<L>(bs, T.in[1], i, j);
+            const MP<L> b21 = ld<L>(bs, T.in[2], i, j), b22 = ld<L>(bs, T.in[3], i, j);
+            const MP<L> s5 = sub_rn<L>(b12, b11);
+            const MP<L> s6 = sub_rn<L>(b22, s5);
+            st<L>(bs, T.out[0], i, j, s5);
+            st<L>(bs, T.out[1], i, j, s6);
+            st<L>(bs, T.out[2], i, j, sub_rn<L>(b22, b12));
+            st<L>(bs, T.out[3], i, j, sub_rn<L>(s6, b21));
+        } else if constexpr (OP == OP_WINO_C) {
+            // T1 = M1 + M2, T2 = T1 + M4; C11 = M2 + M3, C12 = (T1 + M5) + M6,
+            // C21 = T2 - M7, C22 = T2 + M5
+            const MP<L> m1 = ld<L>(bs, T.in[0], i, j), m2 = ld<L>(bs, T.in[1], i, j);
+            const MP<L> m3 = ld<L>(bs, T.in[2], i, j), m4 = ld<L>(bs, T.in[3], i, j);
+            const MP<L> m5 = ld<L>(bs, T.in[4], i, j), m6 = ld<L>(bs, T.in[5], i, j);
+            const MP<L> m7 = ld<L>(bs, T.in[6], i, j);
+            const MP<L> t1 = add_rn<L>(m1, m2);
+            const MP<L> t2 = add_rn<L>(t1, m4);
+            st<L>(bs, T.out[0], i, j, add_rn<L>(m2, m3));
+            st<L>(bs, T.out[1], i, j, add_rn<L>(add_rn<L>(t1, m5), m6));
+            st<L>(bs, T.out[2], i, j, sub_rn<L>(t2, m7));
+            st<L>(bs, T.out[3], i, j, add_rn<L>(t2, m5));
+        } else if constexpr (OP == OP_STR_A) {
+            // A11 + A22, A21 + A22, A11 + A12, A21 - A11, A12 - A22
+            const MP<L> a11 = ld<L>(bs, T.in[0], i, j), a12 = ld<L>(bs, T.in[1], i, j);
+            const MP<L> a21 = ld<L>(bs, T.in[2], i, j), a22 = ld<L>(bs, T.in[3], i, j);
+            st<L>(bs, T.out[0], i, j, add_rn<L>(a11, a22));
+            st<L>(bs, T.out[1], i, j, add_rn<L>(a21, a22));
+            st<L>(bs, T.out[2], i, j, add_rn<L>(a11, a12));
+            st<L>(bs, T.out[3], i, j, sub_rn<L>(a21, a11));
+            st<L>(bs, T.out[4], i, j, sub_rn<L>(a12, a22));
+        } else if constexpr (OP == OP_STR_B) {
+            // B11 + B22, B12 - B22, B21 - B11, B11 + B12, B21 + B22
+            const MP<L> b11 = ld<L>(bs, T.in[0], i, j), b12 = ld<L>(bs, T.in[1], i, j);
+            const MP<L> b21 = ld<L>(bs, T.in[2], i, j), b22 = ld<L>(bs, T.in[3], i, j);
+            st<L>(bs, T.out[0], i, j, add_rn<L>(b11, b22));
+            st<L>(bs, T.out[1], i, j, sub_rn<L>(b12, b22));
+            st<L>(bs, T.out[2], i, j, sub_rn<L>(b21, b11));
+            st<L>(bs, T.out[3], i, j, add_rn<L>(b11, b12));
+            st<L>(bs, T.out[4], i, j, add_rn<L>(b21, b22));
+        } else if constexpr (OP == OP_STR_C) {
+            // C11 = ((P1 + P4) - P5) + P7, C12 = P3 + P5, C21 = P2 + P4,
+            // C22 = ((P1 + P3) - P2) + P6
+            const MP<L> p1 = ld<L>(bs, T.in[0], i, j), p2 = ld<L>(bs, T.in[1], i, j);
+            const MP<L> p3 = ld<L>(bs, T.in[2], i, j), p4 = ld<L>(bs, T.in[3], i, j);
+            const MP<L> p5 = ld<L>(bs, T.in[4], i, j), p6 = ld<L>(bs, T.in[5], i, j);
+            const MP<L> p7 = ld<L>(bs, T.in[6], i, j);
+            st<L>(bs, T.out[0], i, j, add_rn<L>(sub_rn<L>(add_rn<L>(p1, p4), p5), p7));
+            st<L>(bs, T.out[1], i, j, add_rn<L>(p3, p5));
+            st<L>(bs, T.out[2], i, j, add_rn<L>(p2, p4));
+            st<L>(bs, T.out[3], i, j, add_rn<L>(sub_rn<L>(add_rn<L>(p1, p3), p2), p6));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int L>
+static hipError_t gemm_launch_L(int kind, const GemmTask* tasks, const int32_t* tile_task, int64_t ntiles,
+                                const Bases& bs, int64_t grid, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 g((unsigned)grid);
+    if (kind == LEAF_BLOCK)
+        hipLaunchKernelGGL((k_gemm_block<L, GEMM_TM, BLOCK_TK>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles, bs);
+    else
+        hipLaunchKernelGGL((k_gemm_simple<L, GEMM_TM>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(int L, int kind, const GemmTask* tasks, const int32_t* tile_task, int64_t ntiles,
+                       const Bases& bs, int64_t grid, hipStream_t s)
+{
+    switch (L) {
+    case 4: return gemm_launch_L<4>(kind, tasks, tile_task, ntiles, bs, grid, s);
+    case 8: return gemm_launch_L<8>(kind, tasks, tile_task, ntiles, bs, grid, s);
+    case 16: return gemm_launch_L<16>(kind, tasks, tile_task, ntiles, bs, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int L, int OP>
+static void node_launch_one(const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles, const Bases& bs,
+                            int64_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_node<L, OP>), dim3((unsigned)grid), dim3(NODE_TILE), 0, s, tasks, tile_task, ntiles, bs);
+}
+
+template <int L>
+static hipError_t node_launch_L(int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,
+                                const Bases& bs, int64_t grid, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    switch (op) {
+    case OP_ADD: node_launch_one<L, OP_ADD>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_SUB: node_launch_one<L, OP_SUB>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_MUL: node_launch_one<L, OP_MUL>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_DIV: node_launch_one<L, OP_DIV>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_COPY: node_launch_one<L, OP_COPY>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_PADCOPY: node_launch_one<L, OP_PADCOPY>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_WINO_A: node_launch_one<L, OP_WINO_A>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_WINO_B: node_launch_one<L, OP_WINO_B>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_WINO_C: node_launch_one<L, OP_WINO_C>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_STR_A: node_launch_one<L, OP_STR_A>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_STR_B: node_launch_one<L, OP_STR_B>(tasks, tile_task, ntiles, bs, grid, s); break;
+    case OP_STR_C: node_launch_one<L, OP_STR_C>(tasks, tile_task, ntiles, bs, grid, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,
+                       const Bases& bs, int64_t grid, hipStream_t s)
+{
+    switch (L) {
+    case 4: return node_launch_L<4>(op, tasks, tile_task, ntiles, bs, grid, s);
+    case 8: return node_launch_L<8>(op, tasks, tile_task, ntiles, bs, grid, s);
+    case 16: return node_launch_L<16>(op, tasks, tile_task, ntiles, bs, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mpg

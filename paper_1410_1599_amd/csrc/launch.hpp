@@ -1,0 +1,37 @@
+// launch.hpp -- host-side entry points of the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tasks.hpp"
+
+namespace mpg {
+
+constexpr int GEMM_TM = 4;          // rows (waves) per workgroup of a leaf product
+constexpr int BLOCK_TK = 8;         // k-depth of one LDS stage of the Block kernel
+
+enum LeafKind { LEAF_SIMPLE = 0, LEAF_BLOCK = 1 };
+
+// grouped leaf products; tile_task[t] is the index (into tasks) of tile t's task
+hipError_t launch_gemm(int L, int kind, const GemmTask* tasks, const int32_t* tile_task, int64_t ntiles,
+                       const Bases& bs, int64_t grid, hipStream_t s);
+
+// grouped elementwise / per-node passes
+hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,
+                       const Bases& bs, int64_t grid, hipStream_t s);
+
+// LU building blocks (lu_kernels.hip); the matrix is one MatRef on base A
+hipError_t launch_lu_pivot(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int32_t* piv, int32_t* info,
+                           hipStream_t s);
+hipError_t launch_lu_swap(int L, const Bases& bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0,
+                          int64_t col1, hipStream_t s);
+hipError_t launch_lu_scale(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, hipStream_t s);
+hipError_t launch_lu_rank1(int L, const Bases& bs, MatRef a, int64_t t, int64_t r0, int64_t r1, int64_t c0,
+                           int64_t c1, hipStream_t s);
+hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1,
+                           int64_t col0, int64_t col1, int64_t ncols_total, hipStream_t s);
+hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n,
+                           hipStream_t s);
+
+}  // namespace mpg

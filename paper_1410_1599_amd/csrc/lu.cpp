@@ -1,0 +1,120 @@
+// lu.cpp -- host driver of the blocked LU with partial pivoting (Section 4)
+// and of the solve; the C-ABI functions mp_lu, mp_lu_ex and mp_lu_solve.
+//
+// For each panel of K columns starting at j0 (the last one may be narrower):
+//   per column c: pivot search, row swap inside the panel, multipliers
+//   a_ic / a_cc, rank-one update of the panel's remaining columns;
+//   then the panel's swaps on the columns left and right of it;
+//   U12 := L11^-1 A12 by one rank-one update of the panel rows per column t;
+//   P := L21 U12 with the chosen product algorithm, then A22 := A22 - P.
+// Every element therefore sees the operation sequence of the CPU oracle.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.hpp"
+#include "mpgemm_internal.hpp"
+#include "plan.hpp"
+
+using namespace mpg;
+
+namespace {
+
+#define MPG_TRY(expr)                                                    \
+    do {                                                                 \
+        hipError_t e_ = (expr);                                          \
+        if (e_ != hipSuccess) {                                          \
+            g_err = std::string("launch failed: ") + hipGetErrorString(e_); \
+            return MP_E_DEVICE;                                          \
+        }                                                                \
+    } while (0)
+
+int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info_host, int panel,
+           int algo, int cutoff, int policy, hipStream_t s)
+{
+    int rc = MP_OK;
+    const int64_t m2max = n > panel ? n - panel : 0;
+    const size_t pwords = (size_t)(L + 2) * (size_t)(m2max * m2max);
+    // aux buffer: the trailing product P, then one int32 status word
+    uint32_t* aux = workspace(pwords + 64, s, WS_LU, &rc);
+    if (rc) return rc;
+    int32_t* status = (int32_t*)(aux + pwords);
+    MPG_TRY(hipMemsetAsync(status, 0, sizeof(int32_t), s));
+    Bases bs{};
+    bs.p[BASE_A] = A;
+    const MatRef a{BASE_A, 0, 0, lda, psa};
+    for (int64_t j0 = 0; j0 < n; j0 += panel) {
+        const int64_t kb = (panel < n - j0) ? panel : n - j0;
+        const int64_t je = j0 + kb;
+        for (int64_t c = j0; c < je; c++) {
+            MPG_TRY(launch_lu_pivot(L, bs, a, n, c, piv, status, s));
+            MPG_TRY(launch_lu_swap(L, bs, a, c, piv, j0, je, s));
+            MPG_TRY(launch_lu_scale(L, bs, a, n, c, s));
+            MPG_TRY(launch_lu_rank1(L, bs, a, c, c + 1, n, c + 1, je, s));
+        }
+        MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, n, s));
+        MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, je, n, n, s));
+        if (je >= n) break;
+        for (int64_t t = j0; t < je - 1; t++) MPG_TRY(launch_lu_rank1(L, bs, a, t, t + 1, je, je, n, s));
+        const int64_t m2 = n - je;
+        uint32_t* P = aux;
+        const uint32_t* L21 = A + je * lda + j0;
+        const uint32_t* U12 = A + j0 * lda + je;
+        uint32_t* A22 = A + je * lda + je;
+        if ((rc = gemm_internal(m2, kb, m2, L, algo, cutoff, policy, g_leaf, L21, lda, psa, U12, lda, psa, P, m2,
+                                m2 * m2, s)))
+            return rc;
+        if ((rc = ew_internal(OP_SUB, m2, m2, L, A22, lda, psa, P, m2, m2 * m2, A22, lda, psa, s))) return rc;
+    }
+    MPG_TRY(hipMemcpyAsync(info_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MPG_TRY(hipStreamSynchronize(s));
+    return MP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mp_lu_ex(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info, int panel,
+             int algo, int cutoff, int policy)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if (!info) return set_err(MP_E_ARG, "info is NULL");
+    *info = 0;
+    if ((rc = check_mat("A", A, n, n, lda, psa))) return rc;
+    if (panel < 1) return set_err(MP_E_ARG, "panel must be >= 1");
+    if (algo < ALGO_SIMPLE || algo > ALGO_WINOGRAD) return set_err(MP_E_ARG, "unknown algorithm");
+    if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
+    if (policy < POLICY_PEEL || policy > POLICY_MIXED) return set_err(MP_E_ARG, "unknown odd-size policy");
+    if (n == 0) return MP_OK;
+    if (!piv) return set_err(MP_E_ARG, "piv is NULL");
+    if ((rc = device_check())) return rc;
+    if ((rc = lu_run(n, L, A, lda, psa, piv, info, panel, algo, cutoff, policy, g_stream))) return rc;
+    return device_check();
+}
+
+int mp_lu(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info)
+{
+    return mp_lu_ex(n, prec, A, lda, psa, piv, info, 64, ALGO_WINOGRAD, 32, g_policy);
+}
+
+int mp_lu_solve(int64_t n, int prec, const uint32_t* LU, int64_t lda, int64_t psa, const int32_t* piv, uint32_t* b,
+                int64_t psb)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if ((rc = check_mat("LU", LU, n, n, lda, psa)) || (rc = check_mat("b", b, n, 1, 1, psb))) return rc;
+    if (n == 0) return MP_OK;
+    if (!piv) return set_err(MP_E_ARG, "piv is NULL");
+    if (overlaps(b, psb, LU, psa, L)) return set_err(MP_E_ALIAS, "b overlaps LU");
+    if ((rc = device_check())) return rc;
+    Bases bs{};
+    bs.p[BASE_A] = const_cast<uint32_t*>(LU);
+    bs.p[BASE_B] = b;
+    const MatRef lu{BASE_A, 0, 0, lda, psa};
+    const MatRef x{BASE_B, 0, 0, 1, psb};
+    MPG_TRY(launch_lu_solve(L, bs, lu, x, piv, n, g_stream));
+    return device_check();
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+// lu_kernels.hip -- the steps of blocked LU with partial pivoting (Section 4)
+// and of the triangular solves.  The matrix is one MatRef; every element
+// update is c := sub_rn(c, mul_rn(l, u)), so each element sees the same
+// sequence of correctly rounded operations as the CPU oracle.
+#include "launch.hpp"
+#include "mp_arith.hpp"
+
+namespace mpg {
+
+namespace {
+
+template <int L>
+__device__ __forceinline__ MP<L> ldm(const Bases& bs, const MatRef& r, int64_t i, int64_t j)
+{
+    return load<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j);
+}
+
+template <int L>
+__device__ __forceinline__ void stm(const Bases& bs, const MatRef& r, int64_t i, int64_t j, const MP<L>& v)
+{
+    store<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j, v);
+}
+
+constexpr int PIV_THREADS = 1024;
+
+// pivot of column c: the smallest row index i >= c with the largest |a_ic|
+template <int L>
+__global__ void __launch_bounds__(PIV_THREADS)
+k_lu_pivot(Bases bs, MatRef a, int64_t n, int64_t c, int32_t* piv, int32_t* info)
+{
+    __shared__ int32_t sidx[PIV_THREADS];
+    const int tid = threadIdx.x;
+    int32_t best = -1;
+    MP<L> bv = mp_zero<L>();
+    for (int64_t i = c + tid; i < n; i += PIV_THREADS) {
+        const MP<L> v = ldm<L>(bs, a, i, c);
+        if (best < 0 || cmp_abs<L>(v, bv) > 0) {     // ascending scan: ties keep the first
+            best = (int32_t)i;
+            bv = v;
+        }
+    }
+    sidx[tid] = best;
+    __syncthreads();
+    for (int s = PIV_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            const int32_t i1 = sidx[tid], i2 = sidx[tid + s];
+            if (i2 >= 0) {
+                if (i1 < 0) {
+                    sidx[tid] = i2;
+                } else {
+                    const int cm = cmp_abs<L>(ldm<L>(bs, a, i2, c), ldm<L>(bs, a, i1, c));
+                    if (cm > 0 || (cm == 0 && i2 < i1)) sidx[tid] = i2;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int32_t r = sidx[0];
+        piv[c] = r;
+        if (is_zero<L>(ldm<L>(bs, a, r, c)) && info[0] == 0) info[0] = (int32_t)(c + 1);
+    }
+}
+
+// swap rows c and piv[c] over columns [col0, col1)
+template <int L>
+__global__ void __launch_bounds__(256)
+k_lu_swap(Bases bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0, int64_t col1)
+{
+    const int64_t j = col0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= col1) return;
+    const int64_t r = piv[c];
+    if (r == c) return;
+    uint32_t* p = bs.p[a.base] + a.off;
+#pragma unroll
+    for (int k = 0; k < L + 2; k++) {
+        uint32_t* x = p + k * a.ps + c * a.ld + j;
+        uint32_t* y = p + k * a.ps + r * a.ld + j;
+        const uint32_t t = *x;
+        *x = *y;
+        *y = t;
+    }
+}
+
+// multipliers of column c: a_ic := a_ic / a_cc for i in (c, n)
+template <int L>
+__global__ void __launch_bounds__(256)
+k_lu_scale(Bases bs, MatRef a, int64_t n, int64_t c)
+{
+    const int64_t i = c + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const MP<L> d = ldm<L>(bs, a, c, c);
+    stm<L>(bs, a, i, c, div_rn<L>(ldm<L>(bs, a, i, c), d));
+}
+
+// rank-one update: a_rj := a_rj - a_rt a_tj for r in [r0, r1), j in [c0, c1)
+template <int L>
+__global__ void __launch_bounds__(256)
+k_lu_rank1(Bases bs, MatRef a, int64_t t, int64_t r0, int64_t r1, int64_t c0, int64_t c1)
+{
+    const int64_t w = c1 - c0;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (r1 - r0) * w) return;
+    const int64_t r = r0 + e / w, j = c0 + e % w;
+    const MP<L> l = ldm<L>(bs, a, r, t);
+    const MP<L> u = ldm<L>(bs, a, t, j);
+    stm<L>(bs, a, r, j, sub_rn<L>(ldm<L>(bs, a, r, j), mul_rn<L>(l, u)));
+}
+
+// apply the swaps piv[k0 .. k1) in order to columns [col0, col1)
+template <int L>
+__global__ void __launch_bounds__(256)
+k_lu_laswp(Bases bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1, int64_t col0, int64_t col1)
+{
+    const int64_t j = col0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= col1) return;
+    uint32_t* p = bs.p[a.base] + a.off;
+    for (int64_t k = k0; k < k1; k++) {
+        const int64_t r = piv[k];
+        if (r == k) continue;
+#pragma unroll
+        for (int q = 0; q < L + 2; q++) {
+            uint32_t* x = p + q * a.ps + k * a.ld + j;
+            uint32_t* y = p + q * a.ps + r * a.ld + j;
+            const uint32_t t = *x;
+            *x = *y;
+            *y = t;
+        }
+    }
+}
+
+// x := U^-1 L^-1 P b in one workgroup (the vector lives in global memory and
+// every step is separated by a workgroup barrier)
+constexpr int SOLVE_THREADS = 1024;
+
+template <int L>
+__global__ void __launch_bounds__(SOLVE_THREADS)
+k_lu_solve(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        for (int64_t k = 0; k < n; k++) {
+            const int64_t r = piv[k];
+            if (r == k) continue;
+            const MP<L> u = ldm<L>(bs, x, k, 0), v = ldm<L>(bs, x, r, 0);
+            stm<L>(bs, x, k, 0, v);
+            stm<L>(bs, x, r, 0, u);
+        }
+    }
+    __syncthreads();
+    for (int64_t t = 0; t < n; t++) {                 // L y = P b, unit diagonal
+        const MP<L> yt = ldm<L>(bs, x, t, 0);
+        for (int64_t r = t + 1 + tid; r < n; r += SOLVE_THREADS)
+            stm<L>(bs, x, r, 0, sub_rn<L>(ldm<L>(bs, x, r, 0), mul_rn<L>(ldm<L>(bs, lu, r, t), yt)));
+        __syncthreads();
+    }
+    for (int64_t t = n - 1; t >= 0; t--) {            // U x = y
+        if (tid == 0) stm<L>(bs, x, t, 0, div_rn<L>(ldm<L>(bs, x, t, 0), ldm<L>(bs, lu, t, t)));
+        __syncthreads();
+        const MP<L> xt = ldm<L>(bs, x, t, 0);
+        for (int64_t r = tid; r < t; r += SOLVE_THREADS)
+            stm<L>(bs, x, r, 0, sub_rn<L>(ldm<L>(bs, x, r, 0), mul_rn<L>(ldm<L>(bs, lu, r, t), xt)));
+        __syncthreads();
+    }
+}
+
+unsigned blocks_for(int64_t n, int per)
+{
+    return (unsigned)((n + per - 1) / per);
+}
+
+}  // namespace
+
+#define MPG_DISPATCH_L(L_, CALL)           \
+    switch (L_) {                          \
+    case 4: { constexpr int LL = 4; CALL; break; }   \
+    case 8: { constexpr int LL = 8; CALL; break; }   \
+    case 16: { constexpr int LL = 16; CALL; break; } \
+    default: return hipErrorInvalidValue;  \
+    }
+
+hipError_t launch_lu_pivot(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int32_t* piv, int32_t* info,
+                           hipStream_t s)
+{
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_pivot<LL>), dim3(1), dim3(PIV_THREADS), 0, s, bs, a, n, c, piv, info));
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_swap(int L, const Bases& bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0,
+                          int64_t col1, hipStream_t s)
+{
+    if (col1 <= col0) return hipSuccess;
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_swap<LL>), dim3(blocks_for(col1 - col0, 256)), dim3(256), 0, s, bs, a,
+                                         c, piv, col0, col1));
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_scale(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, hipStream_t s)
+{
+    if (n - c - 1 <= 0) return hipSuccess;
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_scale<LL>), dim3(blocks_for(n - c - 1, 256)), dim3(256), 0, s, bs, a,
+                                         n, c));
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_rank1(int L, const Bases& bs, MatRef a, int64_t t, int64_t r0, int64_t r1, int64_t c0,
+                           int64_t c1, hipStream_t s)
+{
+    if (r1 <= r0 || c1 <= c0) return hipSuccess;
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_rank1<LL>), dim3(blocks_for((r1 - r0) * (c1 - c0), 256)), dim3(256),
+                                         0, s, bs, a, t, r0, r1, c0, c1));
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1,
+                           int64_t col0, int64_t col1, int64_t /*ncols_total*/, hipStream_t s)
+{
+    if (col1 <= col0 || k1 <= k0) return hipSuccess;
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_laswp<LL>), dim3(blocks_for(col1 - col0, 256)), dim3(256), 0, s, bs,
+                                         a, piv, k0, k1, col0, col1));
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n,
+                           hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve<LL>), dim3(1), dim3(SOLVE_THREADS), 0, s, bs, lu, x, piv, n));
+    return hipGetLastError();
+}
+
+}  // namespace mpg

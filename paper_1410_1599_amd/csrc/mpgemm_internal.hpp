@@ -1,0 +1,36 @@
+// mpgemm_internal.hpp -- helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mpgemm.h"
+
+namespace mpg {
+
+extern thread_local hipStream_t g_stream;
+extern thread_local std::string g_err;
+extern int g_leaf;
+extern int g_policy;
+
+int set_err(int code, const char* msg);
+int check_prec(int prec, int* L);
+int check_mat(const char* name, const uint32_t* p, int64_t rows, int64_t cols, int64_t ld, int64_t ps);
+bool overlaps(const uint32_t* a, int64_t psa, const uint32_t* b, int64_t psb, int L);
+int device_check();
+enum WsSlot { WS_PLAN = 0, WS_LU = 1 };
+// per-stream, per-slot device buffer of at least `words` uint32 (grown on demand)
+uint32_t* workspace(size_t words, hipStream_t s, int slot, int* rc);
+
+// C := A B through a cached plan (no argument checks)
+int gemm_internal(int64_t m, int64_t l, int64_t n, int L, int algo, int cutoff, int policy, int leaf,
+                  const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
+                  uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s);
+
+// C := A op B elementwise through a cached one-task plan (no argument checks)
+int ew_internal(int op, int64_t m, int64_t n, int L, const uint32_t* A, int64_t lda, int64_t psa,
+                const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s);
+
+}  // namespace mpg

@@ -1,0 +1,190 @@
+"""Python binding of libmpgemm (include/mpgemm.h): argument marshalling only.
+
+Matrices are torch tensors on the GPU in the library's plane layout: shape
+(L + 2, rows, ld), dtype int32 (the words are reinterpreted as uint32 by the
+library), last dimension contiguous; ld = stride(1), plane stride = stride(0).
+Every function here forwards to the C function of the same name on torch's
+current stream.  If the library is missing or cannot be loaded the import of
+this module fails: there is no fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmpgemm.so")
+
+SIMPLE, BLOCK, STRASSEN, WINOGRAD = 0, 1, 2, 3
+ALGOS = {"simple": SIMPLE, "block": BLOCK, "strassen": STRASSEN, "winograd": WINOGRAD}
+PEEL, PAD, MIXED = 0, 1, 2
+POLICIES = {"peel": PEEL, "pad": PAD, "mixed": MIXED}
+LEAF_SIMPLE, LEAF_BLOCK = 0, 1
+
+MP_OK = 0
+
+
+class MPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libmpgemm error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError("libmpgemm.so is not built (run python -m paper_1410_1599_amd.build)")
+    lib = ctypes.CDLL(LIBPATH)
+    i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+    dp, i32p, i64p = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)
+    mat = [vp, i64, i64]
+    sig = {
+        "mp_set_stream": ([vp], i32),
+        "mp_last_error": ([], ctypes.c_char_p),
+        "mp_version": ([], i32),
+        "mp_set_policy": ([i32, i32], i32),
+        "mp_gemm": ([i64, i64, i64, i32, i32, i32] + mat * 3, i32),
+        "mp_gemm_ex": ([i64, i64, i64, i32, i32, i32, i32, i32] + mat * 3, i32),
+        "mp_add": ([i64, i64, i32] + mat * 3, i32),
+        "mp_sub": ([i64, i64, i32] + mat * 3, i32),
+        "mp_mul_ew": ([i64, i64, i32] + mat * 3, i32),
+        "mp_div_ew": ([i64, i64, i32] + mat * 3, i32),
+        "mp_plan_info": ([i64, i64, i64, i32, i32, i32, i32, i32p, dp, dp, i64p, i64p], i32),
+        "mp_lu": ([i64, i32, vp, i64, i64, vp, i32p], i32),
+        "mp_lu_ex": ([i64, i32, vp, i64, i64, vp, i32p, i32, i32, i32, i32], i32),
+        "mp_lu_solve": ([i64, i32, vp, i64, i64, vp, vp, i64], i32),
+        "mp_release_workspace": ([], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def last_error():
+    return lib.mp_last_error().decode()
+
+
+def _check(rc):
+    if rc != MP_OK:
+        raise MPError(rc, last_error())
+    return rc
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _mat(t):
+    """(pointer, ld, plane stride) of a plane-layout tensor."""
+    if t is None:
+        return (None, 0, 0)
+    if t.dim() != 3 or t.stride(2) != 1:
+        raise ValueError("matrix tensors are (L + 2, rows, ld) with a contiguous last dimension")
+    return (ctypes.c_void_p(t.data_ptr()), t.stride(1), t.stride(0))
+
+
+def nlimbs(prec):
+    return prec // 32
+
+
+# ----------------------------------------------------------------- tensors
+
+def to_device(planes, device="cuda"):
+    """numpy uint32 planes (L + 2, rows, ld) -> int32 torch tensor on the GPU."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(planes).view(np.int32)).to(device)
+
+
+def to_host(t):
+    """torch plane tensor -> numpy uint32 planes."""
+    return t.detach().cpu().contiguous().numpy().view(np.uint32)
+
+
+def empty(rows, cols, prec, device="cuda"):
+    import torch
+    return torch.zeros((nlimbs(prec) + 2, rows, cols), dtype=torch.int32, device=device)
+
+
+# ----------------------------------------------------------------- the C functions
+
+def mp_set_stream(stream=None):
+    return _check(lib.mp_set_stream(stream if stream is not None else _stream()))
+
+
+def mp_set_policy(odd_policy=PEEL, leaf=LEAF_SIMPLE):
+    return _check(lib.mp_set_policy(int(odd_policy), int(leaf)))
+
+
+def mp_gemm(m, l, n, prec, algo, cutoff, A, B, C):
+    mp_set_stream()
+    return _check(lib.mp_gemm(m, l, n, prec, int(algo), int(cutoff), *_mat(A), *_mat(B), *_mat(C)))
+
+
+def mp_gemm_ex(m, l, n, prec, algo, cutoff, policy, leaf, A, B, C):
+    mp_set_stream()
+    return _check(lib.mp_gemm_ex(m, l, n, prec, int(algo), int(cutoff), int(policy), int(leaf),
+                                 *_mat(A), *_mat(B), *_mat(C)))
+
+
+def _ew(fn, m, n, prec, A, B, C):
+    mp_set_stream()
+    return _check(fn(m, n, prec, *_mat(A), *_mat(B), *_mat(C)))
+
+
+def mp_add(m, n, prec, A, B, C):
+    return _ew(lib.mp_add, m, n, prec, A, B, C)
+
+
+def mp_sub(m, n, prec, A, B, C):
+    return _ew(lib.mp_sub, m, n, prec, A, B, C)
+
+
+def mp_mul_ew(m, n, prec, A, B, C):
+    return _ew(lib.mp_mul_ew, m, n, prec, A, B, C)
+
+
+def mp_div_ew(m, n, prec, A, B, C):
+    return _ew(lib.mp_div_ew, m, n, prec, A, B, C)
+
+
+def mp_plan_info(m, l, n, prec, algo, cutoff, policy=PEEL):
+    d = ctypes.c_int(0)
+    nm, na = ctypes.c_double(0), ctypes.c_double(0)
+    ws, nl = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib.mp_plan_info(m, l, n, prec, int(algo), int(cutoff), int(policy), ctypes.byref(d),
+                            ctypes.byref(nm), ctypes.byref(na), ctypes.byref(ws), ctypes.byref(nl)))
+    return {"depth": d.value, "n_mul": nm.value, "n_addsub": na.value, "ws_bytes": ws.value, "n_launches": nl.value}
+
+
+def mp_lu(n, prec, A, piv):
+    mp_set_stream()
+    info = ctypes.c_int(0)
+    pa, lda, psa = _mat(A)
+    _check(lib.mp_lu(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()), ctypes.byref(info)))
+    return info.value
+
+
+def mp_lu_ex(n, prec, A, piv, panel=64, algo=WINOGRAD, cutoff=32, policy=PEEL):
+    mp_set_stream()
+    info = ctypes.c_int(0)
+    pa, lda, psa = _mat(A)
+    _check(lib.mp_lu_ex(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()), ctypes.byref(info),
+                        int(panel), int(algo), int(cutoff), int(policy)))
+    return info.value
+
+
+def mp_lu_solve(n, prec, LU, piv, b):
+    mp_set_stream()
+    pa, lda, psa = _mat(LU)
+    pb, _, psb = _mat(b)
+    return _check(lib.mp_lu_solve(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()), pb, psb))
+
+
+def mp_release_workspace():
+    return _check(lib.mp_release_workspace())

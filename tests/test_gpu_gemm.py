@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+* scalar primitives (elementwise mul/add/sub/div) on adversarial operands;
+* the n = 64, 128-bit workload as Simple, Block and one Winograd level
+  (cutoff 32), against the Python oracle, full matrix;
+* ragged shapes spanning several tiles, every algorithm and odd-size policy
+  at small cutoffs, both leaf kernels, against the C oracle;
+* few-bit (tie-heavy), log-uniform and small-integer inputs;
+* edge cases: empty dimensions, inner size 0 and 1, strided sub-matrix
+  views, aliasing and argument errors.
+"""
+
+import random
+
+import numpy as np
+import pytest
+
+from helpers import adversarial_pairs, first_mismatch, planes_equal, random_value, vec_planes
+from oracle import cref, gemm as G, mpnum
+from paper_1410_1599_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1410_1599_amd import mp  # noqa: E402  (fails loudly if the library is missing)
+
+
+def sync():
+    torch.cuda.synchronize()
+
+
+def gpu_gemm(A, B, p, algo, cutoff=32, policy=mp.PEEL, leaf=mp.LEAF_SIMPLE, C0=None):
+    m, l = A.shape[1], A.shape[2]
+    n = B.shape[2]
+    dA, dB = mp.to_device(A), mp.to_device(B)
+    dC = mp.empty(m, n, p) if C0 is None else mp.to_device(C0)
+    mp.mp_gemm_ex(m, l, n, p, algo, cutoff, policy, leaf, dA, dB, dC)
+    sync()
+    return mp.to_host(dC)
+
+
+def assert_same(got, want, p, what=""):
+    if not planes_equal(got, want):
+        raise AssertionError("%s: mismatch %s" % (what, first_mismatch(got, want, p)))
+
+
+# ------------------------------------------------------------- primitives
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_scalar_ops_adversarial(p):
+    rng = random.Random(500 + p)
+    pairs = adversarial_pairs(rng, p) + [(random_value(rng, p, -40, 40), random_value(rng, p, -40, 40)) for _ in range(2000)]
+    X = vec_planes([x for x, _ in pairs], p)
+    Y = vec_planes([y for _, y in pairs], p)
+    dX, dY = mp.to_device(X), mp.to_device(Y)
+    N = len(pairs)
+    for name, fn, ref in (("mul", mp.mp_mul_ew, mpnum.mul), ("add", mp.mp_add, mpnum.add),
+                          ("sub", mp.mp_sub, mpnum.sub), ("div", mp.mp_div_ew, mpnum.div)):
+        dZ = mp.empty(1, N, p)
+        if name == "div":
+            keep = [k for k, (_, y) in enumerate(pairs) if y[0] != 0]
+        else:
+            keep = list(range(N))
+        fn(1, N, p, dX, dY, dZ)
+        sync()
+        Z = mp.to_host(dZ)
+        for k in keep:
+            x, y = pairs[k]
+            want = ref(x, y, p)
+            got = I.entry(Z, 0, k, p)
+            assert got == want, (name, p, x, y, got, want)
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_division_random_mantissas(p):
+    rng = random.Random(900 + p)
+    pairs = [(random_value(rng, p, -300, 300), random_value(rng, p, -300, 300)) for _ in range(3000)]
+    # divisors with long runs of ones / zeros stress the digit estimate
+    one = 1 << (p - 1)
+    for _ in range(500):
+        run = rng.randrange(1, p)
+        pairs.append(((rng.randrange(one, 1 << p), 0), (((1 << p) - 1) ^ ((1 << run) - 1) | one, 0)))
+        pairs.append(((rng.randrange(one, 1 << p), 0), (one | ((1 << run) - 1), 0)))
+        pairs.append((((1 << p) - 1 - rng.randrange(0, 1 << 16), 0), (one + rng.randrange(0, 1 << 16), 0)))
+    X = vec_planes([x for x, _ in pairs], p)
+    Y = vec_planes([y for _, y in pairs], p)
+    dZ = mp.empty(1, len(pairs), p)
+    mp.mp_div_ew(1, len(pairs), p, mp.to_device(X), mp.to_device(Y), dZ)
+    sync()
+    Z = mp.to_host(dZ)
+    for k, (x, y) in enumerate(pairs):
+        assert I.entry(Z, 0, k, p) == mpnum.div(x, y, p), (x, y)
+
+
+# ------------------------------------------------------------- the n = 64 workload
+
+@pytest.mark.parametrize("algo,cutoff", [("simple", 0), ("block", 0), ("winograd", 32), ("strassen", 32)])
+def test_n64_p128_against_python_oracle(algo, cutoff):
+    p, n = 128, 64
+    A = I.uniform_pm1(n, n, p, 1)
+    B = I.uniform_pm1(n, n, p, 2)
+    Ao, Bo = I.from_planes(A, p), I.from_planes(B, p)
+    want = I.to_planes(G.gemm(Ao, Bo, p, algo=algo, cutoff=max(cutoff, 1), block_size=16), p)
+    got = gpu_gemm(A, B, p, mp.ALGOS[algo], cutoff=max(cutoff, 1))
+    assert_same(got, want, p, algo)
+    if algo == "winograd":
+        assert G.depth(n, n, n, 32) == 1
+
+
+# ------------------------------------------------------------- ragged shapes
+
+SHAPES = [(1, 1, 1), (1, 7, 1), (5, 1, 9), (9, 9, 9), (31, 33, 35), (33, 31, 66), (63, 65, 67),
+          (67, 64, 63), (130, 7, 129), (100, 130, 70), (257, 33, 5)]
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("algo", ["simple", "block", "strassen", "winograd"])
+def test_ragged_shapes_against_c_oracle(p, algo):
+    rng = np.random.default_rng(p)
+    for (m, l, n) in SHAPES:
+        seed = int(rng.integers(0, 1 << 30))
+        A = I.uniform_pm1(m, l, p, seed)
+        B = I.log_uniform(l, n, p, seed + 1, -30, 30)
+        for cutoff in ((4, 16) if algo in ("strassen", "winograd") else (1,)):
+            for policy in (("peel", "pad", "mixed") if algo in ("strassen", "winograd") else ("peel",)):
+                want = cref.gemm(A, B, p, algo=algo, cutoff=cutoff, policy=policy)
+                got = gpu_gemm(A, B, p, mp.ALGOS[algo], cutoff, mp.POLICIES[policy])
+                assert_same(got, want, p, "%s %s %s cut=%d" % (algo, (m, l, n), policy, cutoff))
+
+
+@pytest.mark.parametrize("p", [128, 256])
+def test_block_leaves_in_fast_algorithms(p):
+    A = I.uniform_pm1(100, 90, p, 41)
+    B = I.uniform_pm1(90, 110, p, 42)
+    for algo in ("strassen", "winograd"):
+        want = cref.gemm(A, B, p, algo=algo, cutoff=20)
+        got = gpu_gemm(A, B, p, mp.ALGOS[algo], 20, mp.PEEL, mp.LEAF_BLOCK)
+        assert_same(got, want, p, algo + " block leaves")
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_tie_heavy_and_integer_inputs(p):
+    A = I.sparse_bits(40, 37, p, 7)
+    B = I.sparse_bits(37, 45, p, 8)
+    for algo in ("simple", "winograd", "strassen"):
+        want = cref.gemm(A, B, p, algo=algo, cutoff=5)
+        assert_same(gpu_gemm(A, B, p, mp.ALGOS[algo], 5), want, p, algo + " sparse bits")
+    A = I.integers(33, 20, p, 9)
+    B = I.integers(20, 31, p, 10)
+    for algo in ("simple", "winograd", "strassen"):
+        want = cref.gemm(A, B, p, algo=algo, cutoff=3)
+        assert_same(gpu_gemm(A, B, p, mp.ALGOS[algo], 3), want, p, algo + " integers")
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_empty_and_degenerate_sizes():
+    p = 256
+    for (m, l, n) in ((0, 5, 3), (3, 5, 0), (0, 0, 0)):
+        dA, dB, dC = mp.empty(max(m, 1), max(l, 1), p), mp.empty(max(l, 1), max(n, 1), p), mp.empty(max(m, 1), max(n, 1), p)
+        mp.mp_gemm(m, l, n, p, mp.WINOGRAD, 4, dA, dB, dC)
+    # inner size 0: C = 0
+    C0 = I.uniform_pm1(4, 6, p, 3)
+    dA, dB = mp.empty(4, 1, p), mp.empty(1, 6, p)
+    dC = mp.to_device(C0)
+    mp.mp_gemm(4, 0, 6, p, mp.SIMPLE, 0, dA, dB, dC)
+    sync()
+    assert not mp.to_host(dC).any()
+
+
+def test_strided_views():
+    """Operands and result as sub-matrices of larger buffers (ld > cols, plane
+    stride > rows * ld); the surroundings must stay untouched."""
+    p = 128
+    L = p // 32
+    big = I.uniform_pm1(90, 100, p, 11)
+    A = big[:, 3:3 + 40, 5:5 + 37]          # 40 x 37 view (numpy copy keeps the values)
+    B = I.uniform_pm1(37, 29, p, 12)
+    want = cref.gemm(np.ascontiguousarray(A), B, p, algo="winograd", cutoff=6)
+    dbig = mp.to_device(big)
+    dA = dbig[:, 3:3 + 40, 5:5 + 37]
+    dB = mp.to_device(B)
+    out = I.uniform_pm1(50, 60, p, 13)
+    dout = mp.to_device(out)
+    dC = dout[:, 7:7 + 40, 11:11 + 29]
+    mp.mp_gemm(40, 37, 29, p, mp.WINOGRAD, 6, dA, dB, dC)
+    sync()
+    res = mp.to_host(dout)
+    assert_same(np.ascontiguousarray(res[:, 7:47, 11:40]), want, p, "view")
+    mask = np.ones(res.shape, dtype=bool)
+    mask[:, 7:47, 11:40] = False
+    assert np.array_equal(res[mask], out[mask])
+
+
+def test_argument_errors_launch_nothing():
+    p = 256
+    dA = mp.to_device(I.uniform_pm1(8, 8, p, 1))
+    dB = mp.to_device(I.uniform_pm1(8, 8, p, 2))
+    C0 = I.uniform_pm1(8, 8, p, 3)
+    dC = mp.to_device(C0)
+    with pytest.raises(mp.MPError) as e:
+        mp.mp_gemm(8, 8, 8, 200, mp.SIMPLE, 0, dA, dB, dC)
+    assert e.value.code == -2
+    with pytest.raises(mp.MPError) as e:
+        mp.mp_gemm(8, 8, 8, p, mp.WINOGRAD, 0, dA, dB, dC)
+    assert e.value.code == -1
+    with pytest.raises(mp.MPError) as e:
+        mp.mp_gemm(8, 8, 8, p, mp.SIMPLE, 0, dA, dB, dA)
+    assert e.value.code == -3
+    with pytest.raises(mp.MPError) as e:
+        mp.mp_gemm(8, 9, 8, p, mp.SIMPLE, 0, dA, dB, dC)     # ld of A < l
+    assert e.value.code == -1
+    sync()
+    assert np.array_equal(mp.to_host(dC), C0)
+
+
+def test_repeat_calls_are_deterministic():
+    p = 512
+    A = I.uniform_pm1(70, 80, p, 21)
+    B = I.uniform_pm1(80, 75, p, 22)
+    r1 = gpu_gemm(A, B, p, mp.WINOGRAD, 16)
+    r2 = gpu_gemm(A, B, p, mp.WINOGRAD, 16)
+    assert planes_equal(r1, r2)
+    assert_same(r1, cref.gemm(A, B, p, algo="winograd", cutoff=16), p, "512-bit winograd")

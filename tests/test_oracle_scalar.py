@@ -22,6 +22,8 @@ from mpmath import libmp
 from oracle import mpnum, cref
 from paper_1410_1599_amd import inputs as I
 
+from helpers import adversarial_pairs, random_value
+
 
 # ------------------------------------------------------------- brute force
 
@@ -104,37 +106,6 @@ def test_from_fraction_brute():
 def to_mpf(v, p):
     sig, e = v
     return libmp.from_man_exp(sig, e - p) if sig else libmp.fzero
-
-
-def random_value(rng, p, emin=-8, emax=8):
-    return (rng.choice((1, -1)) * rng.randrange(1 << (p - 1), 1 << p), rng.randint(emin, emax))
-
-
-def adversarial_pairs(rng, p):
-    """Operand pairs at the corners of the rounding code."""
-    one = 1 << (p - 1)
-    top = (1 << p) - 1
-    out = []
-    for gap in [0, 1, 2, 31, 32, 33, p - 1, p, p + 1, p + 2, p + 3, p + 4, 2 * p, 10 * p]:
-        for mx in (one, top, rng.randrange(one, 1 << p)):
-            for my in (one, top, rng.randrange(one, 1 << p), one | 1, top - 1):
-                for s in (1, -1):
-                    out.append(((mx, 5), (s * my, 5 - gap)))
-    # exact ties: x + half an ulp of x, at both parities
-    for mx in (one, one + 1, top, top - 1):
-        out.append(((mx, 0), (one, -p)))        # 2**-p-1 ... half ulp of x
-        out.append(((mx, 0), (-one, -p)))
-    # few-bit mantissas: exact products and ties
-    for _ in range(200):
-        a = one | (1 << rng.randrange(0, p - 1))
-        b = one | (1 << rng.randrange(0, p - 1)) | (1 << rng.randrange(0, p - 1))
-        out.append(((rng.choice((1, -1)) * a, rng.randint(-3, 3)), (rng.choice((1, -1)) * b, rng.randint(-3, 3))))
-    # full and near-full cancellation
-    for _ in range(50):
-        m = rng.randrange(one, 1 << p)
-        out.append(((m, 1), (-m, 1)))
-        out.append(((m, 1), (-(m - 1 if m > one else m + 1), 1)))
-    return out
 
 
 @pytest.mark.parametrize("p", [128, 256, 512])
