@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the MP matrix product on one MI355X.
+
+Workload (the metric's configuration): C := A B with m = l = n = 2048 at
+256-bit precision, entries with random sign and log-uniform magnitudes over
+2^-21 .. 2^20 (seeds 6 and 7), every scalar operation rounded to nearest.
+One step is one full product through the C ABI with inputs resident in HBM;
+the headline algorithm is Winograd's variant with cutoff 64 (odd sizes
+peeled), which is bit-identical to the CPU oracle.  The other algorithms are
+timed beside it.
+
+Prints one JSON line: the metric (classical-equivalent rate 2 m l n / s),
+the roofline of the dominant kernel (the grouped leaf-product launch, timed
+with HIP events on its own stream during the timed steps) and the CPU oracle
+timed on a bounded sample of the same product.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# chip figures used for the roofline (256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz)
+CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
+INT_LANE_OPS = CUS * SIMDS * LANES * CLOCK_HZ        # 39.3e12 32-bit VALU lane-ops/s
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--prec", type=int, default=256)
+    ap.add_argument("--algo", default="winograd", choices=["simple", "block", "strassen", "winograd"])
+    ap.add_argument("--cutoff", type=int, default=64)
+    ap.add_argument("--others", type=int, default=2, help="timed steps for each non-headline algorithm (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1410_1599_amd import inputs as I
+    from paper_1410_1599_amd import mp
+
+    n, p = args.n, args.prec
+    L = p // 32
+    A = I.log_uniform(n, n, p, 6)
+    B = I.log_uniform(n, n, p, 7)
+    dA, dB = mp.to_device(A), mp.to_device(B)
+    dC = mp.empty(n, n, p)
+    algo = mp.ALGOS[args.algo]
+
+    def step(al=algo, cut=args.cutoff):
+        mp.mp_gemm_ex(n, n, n, p, al, cut, mp.PEEL, mp.LEAF_SIMPLE, dA, dB, dC)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mp.mp_profile_read()                     # drop anything recorded before
+    mp.mp_profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mp.mp_profile(False)
+    recs = mp.mp_profile_read()
+    ms = (t1 - t0) * 1e3 / args.steps
+    rate = 2.0 * n ** 3 / (ms * 1e-3)
+
+    # dominant kernel: the grouped leaf-product launch
+    leaf = [r for r in recs if r["kind"] == 0]
+    leaf_ms = sum(r["ms"] for r in leaf) / max(1, len(leaf))
+    leaf_units = leaf[0]["units"] if leaf else 0.0          # scalar MP multiply-adds per launch
+    all_ms = sum(r["ms"] for r in recs) / max(1, args.steps)
+    achieved = leaf_units * L * L / (leaf_ms * 1e-3) / 1e12 if leaf_ms > 0 else 0.0
+    peak = INT_LANE_OPS / 1e12
+    roofline = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+        "frac": round(achieved / peak, 4), "traffic": None,
+        "kernel": "k_gemm_simple<L=%d> grouped leaf products" % L,
+        "op": "one 32x32->64-bit limb multiply-accumulate; L^2 = %d per MP multiply-add" % (L * L),
+        "launch_ms": round(leaf_ms, 3), "units_per_launch": leaf_units,
+        "leaf_share_of_step": round(leaf_ms / all_ms, 4) if all_ms else None,
+    }
+
+    # parity spot check of the timed configuration against stored oracle entries
+    parity = None
+    gold = os.path.join(ROOT, "tests", "golden", "full_size_n%d_p%d.json" % (n, p))
+    if os.path.exists(gold) and args.cutoff == 64:
+        g = json.load(open(gold))
+        ents = g["entries"].get(args.algo)
+        if ents and g["kind"] == "log_uniform":
+            C = mp.to_host(dC)
+            bad = 0
+            for i, j, s, e, mh in ents:
+                sig = int(mh, 16) * (-1 if s else 1)
+                if I.entry(C, i, j, p) != (sig, e):
+                    bad += 1
+            parity = "%d of %d sampled entries bit-exact vs the oracle" % (len(ents) - bad, len(ents))
+
+    others = {}
+    if args.others > 0:
+        for name in ("simple", "block", "strassen", "winograd"):
+            if name == args.algo:
+                continue
+            al = mp.ALGOS[name]
+            step(al)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.others):
+                step(al)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / args.others
+            others[name] = {"ms_per_step": round(t * 1e3, 3), "value": 2.0 * n ** 3 / t}
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cref
+        cores = cref.threads()
+        rows = 2
+        # Simple's output rows are independent: time the oracle on the first
+        # rows of the same product, growing the sample to the target length
+        while True:
+            t0 = time.perf_counter()
+            cref.gemm(np.ascontiguousarray(A[:, :rows, :]), B, p, algo="simple", m=rows)
+            t = time.perf_counter() - t0
+            if t > args.cpu_seconds / 4 or rows >= n:
+                break
+            rows = min(n, max(rows * 2, int(rows * args.cpu_seconds / max(t, 1e-3) / 2)))
+        cpu = {"value": 2.0 * rows * n * n / t, "unit": "2mln/s", "cores": cores, "kind": "oracle",
+               "sample": "C oracle (oracle/c/mpref.c), Simple on rows 0..%d of the same 2048^3 256-bit product, "
+                         "%.1f s on %d threads" % (rows - 1, t, cores)}
+
+    out = {
+        "metric": "MP-GEMM 2mln/s at 256-bit n=2048 (limb path)",
+        "value": rate, "unit": "2mln/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "mp_gemm m=l=n=%d prec=%d %s cutoff=%d peel, log-uniform |a| in 2^-21..2^20, "
+                               "seeds 6/7" % (n, p, args.algo, args.cutoff),
+                   "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
+        "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

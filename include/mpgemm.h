@@ -174,6 +174,19 @@ int mp_lu_ex(int64_t n, int prec, uint32_t *A, int64_t lda, int64_t psa, int32_t
 int mp_lu_solve(int64_t n, int prec, const uint32_t *LU, int64_t lda, int64_t psa, const int32_t *piv,
                 uint32_t *b, int64_t psb);
 
+/*
+ * Step profiler.  mp_profile(1) makes every later grouped launch of the
+ * library record a HIP event pair on its own stream; mp_profile(0) stops.
+ * mp_profile_read waits for the recorded launches, writes up to `max` records
+ * (host arrays): kind (0 = leaf products, 1 = elementwise / per-node pass),
+ * op (leaf kernel enum mp_leaf for kind 0, internal pass code for kind 1), L
+ * (limbs), units (scalar multiply-adds for kind 0, elements for kind 1),
+ * ntiles (workgroup tiles) and ms (elapsed milliseconds), clears the record
+ * list and returns the number of records it held.
+ */
+int mp_profile(int enable);
+int mp_profile_read(int max, int *kind, int *op, int *L, double *units, int64_t *ntiles, float *ms);
+
 /* Free the workspaces and cached plans of the current device (synchronises the device). */
 int mp_release_workspace(void);
 

@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "launch.hpp"
 #include "mpgemm_internal.hpp"
@@ -175,6 +176,17 @@ int64_t grid_for(int64_t ntiles)
     return ntiles < (int64_t(1) << 30) ? ntiles : (int64_t(1) << 30);
 }
 
+// ---- step profiler: HIP events around every grouped launch, on its stream
+struct ProfRec {
+    int kind, op, L;
+    double units;
+    int64_t ntiles;
+    hipEvent_t e0, e1;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
 int run_plan(const Plan& P, Bases bs, hipStream_t s)
 {
     int rc = MP_OK;
@@ -183,12 +195,25 @@ int run_plan(const Plan& P, Bases bs, hipStream_t s)
     // the tile map holds indices into the plan's whole task arrays
     for (const Step& st : P.steps) {
         hipError_t e;
+        ProfRec pr{};
+        const bool prof = g_prof_on;
+        if (prof) {
+            pr = ProfRec{st.kind, st.op, P.key.L, st.units, st.ntiles, nullptr, nullptr};
+            (void)hipEventCreate(&pr.e0);
+            (void)hipEventCreate(&pr.e1);
+            (void)hipEventRecord(pr.e0, s);
+        }
         if (st.kind == 0)
             e = launch_gemm(P.key.L, st.op, P.d_gemm, P.d_tiles + st.tile0, st.ntiles, bs,
                             grid_for(st.ntiles), s);
         else
             e = launch_node(P.key.L, st.op, P.d_node, P.d_tiles + st.tile0, st.ntiles, bs,
                             grid_for(st.ntiles), s);
+        if (prof) {
+            (void)hipEventRecord(pr.e1, s);
+            std::lock_guard<std::mutex> g(g_prof_mu);
+            g_prof.push_back(pr);
+        }
         if (e != hipSuccess) {
             g_err = std::string("launch failed: ") + hipGetErrorString(e);
             return MP_E_DEVICE;
@@ -378,6 +403,32 @@ int mp_plan_info(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff
     if (ws_bytes) *ws_bytes = P.ws_words * 4;
     if (n_launches) *n_launches = (int64_t)P.steps.size();
     return MP_OK;
+}
+
+int mp_profile(int enable)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = enable != 0;
+    return MP_OK;
+}
+
+int mp_profile_read(int max, int* kind, int* op, int* L, double* units, int64_t* ntiles, float* ms)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    int n = 0;
+    for (ProfRec& r : g_prof) {
+        if (n < max) {
+            (void)hipEventSynchronize(r.e1);
+            float t = 0;
+            (void)hipEventElapsedTime(&t, r.e0, r.e1);
+            kind[n] = r.kind; op[n] = r.op; L[n] = r.L; units[n] = r.units; ntiles[n] = r.ntiles; ms[n] = t;
+        }
+        n++;
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    g_prof.clear();
+    return n;
 }
 
 int mp_release_workspace(void)

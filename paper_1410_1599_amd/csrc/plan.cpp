@@ -229,6 +229,7 @@ void build_plan(Plan& P, const PlanKey& k)
         int64_t tile = 0;
         for (auto& t : v) {
             t.tile0 = tile;
+            s.units += (double)t.rows * t.cols;
             const int64_t nt = node_tiles(t);
             const int32_t idx = (int32_t)P.node.size();
             P.node.push_back(t);
@@ -244,6 +245,7 @@ void build_plan(Plan& P, const PlanKey& k)
         int64_t tile = 0;
         for (auto& t : v) {
             t.tile0 = tile;
+            s.units += (double)t.m * t.l * t.n;
             const int64_t nt = gemm_tiles(t);
             const int32_t idx = (int32_t)P.gemm.size();
             P.gemm.push_back(t);

@@ -36,6 +36,7 @@ struct Step {
     int op;                    // NodeOp for kind 1, LeafKind for kind 0
     int64_t task0, ntasks;     // range in the plan's gemm or node task array
     int64_t tile0, ntiles;     // range in the plan's tile map
+    double units = 0;          // scalar MP multiply-adds (kind 0) or elements (kind 1)
 };
 
 struct PlanKey {

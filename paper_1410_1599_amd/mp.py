@@ -54,6 +54,8 @@ def _load():
         "mp_lu_ex": ([i64, i32, vp, i64, i64, vp, i32p, i32, i32, i32, i32], i32),
         "mp_lu_solve": ([i64, i32, vp, i64, i64, vp, vp, i64], i32),
         "mp_release_workspace": ([], i32),
+        "mp_profile": ([i32], i32),
+        "mp_profile_read": ([i32, i32p, i32p, i32p, dp, i64p, ctypes.POINTER(ctypes.c_float)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -188,3 +190,16 @@ def mp_lu_solve(n, prec, LU, piv, b):
 
 def mp_release_workspace():
     return _check(lib.mp_release_workspace())
+
+
+def mp_profile(enable):
+    return _check(lib.mp_profile(1 if enable else 0))
+
+
+def mp_profile_read(max_records=4096):
+    """List of dicts (kind, op, L, units, ntiles, ms) of the recorded launches."""
+    n = max_records
+    kind, op, L = (ctypes.c_int * n)(), (ctypes.c_int * n)(), (ctypes.c_int * n)()
+    units, nt, ms = (ctypes.c_double * n)(), (ctypes.c_int64 * n)(), (ctypes.c_float * n)()
+    got = lib.mp_profile_read(n, kind, op, L, units, nt, ms)
+    return [dict(kind=kind[i], op=op[i], L=L[i], units=units[i], ntiles=nt[i], ms=ms[i]) for i in range(min(got, n))]
