@@ -54,12 +54,15 @@ __device__ __forceinline__ uint32_t clz32(uint32_t x)
     return x ? (uint32_t)__builtin_clz(x) : 32u;
 }
 
-// 96-bit column accumulator (acc64 : c2) += a * b
+// 96-bit column accumulator (acc64 : c2) += a * b.  v_mad_u64_u32 returns
+// the carry out of its 64-bit sum in a lane mask, which v_addc adds into c2:
+// two VALU instructions per limb product (the compiler's own lowering
+// recomputes the carry with a 64-bit compare).  Register operands only.
 __device__ __forceinline__ void mac(uint64_t& acc, uint32_t& c2, uint32_t a, uint32_t b)
 {
-    uint64_t p = (uint64_t)a * b;
-    acc += p;
-    c2 += (acc < p) ? 1u : 0u;
+    uint64_t cy, unused;
+    asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(cy) : "v"(a), "v"(b));
+    asm volatile("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(c2), "=s"(unused) : "s"(cy));
 }
 
 template <int L>
@@ -195,9 +198,11 @@ __device__ __forceinline__ MP<L> mul_rn(const MP<L>& a, const MP<L>& b)
 #pragma unroll
     for (int k = 0; k < L; k++) r.m[k] = addc(r.m[k], 0, c, &c);
     if (c) r.m[L - 1] = 0x80000000u;         // 2^p: the others are already 0
-    r.e = a.e + b.e - (n1 ? 0 : 1) + (int32_t)c;
-    r.s = a.s ^ b.s;
-    if (is_zero(a) || is_zero(b)) r = mp_zero<L>();
+    // a zero factor makes H zero, so the mantissa is already zero: only the
+    // exponent and sign need the canonical zero
+    const bool z = is_zero(a) || is_zero(b);
+    r.e = z ? 0 : a.e + b.e - (n1 ? 0 : 1) + (int32_t)c;
+    r.s = z ? 0u : (a.s ^ b.s);
     return r;
 }
 
@@ -306,10 +311,11 @@ __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
         r.m[L - 1] = 0x80000000u;
         e += 1;
     }
-    r.e = e;
-    r.s = X.s;
-    if (zx && zy) r = mp_zero<L>();
-    if (r.m[L - 1] == 0) r = mp_zero<L>();    // exact cancellation -> +0
+    // an exact zero (cancellation, or both operands zero) leaves every limb
+    // zero; give it the canonical exponent and sign (+0)
+    const bool rz = r.m[L - 1] == 0;
+    r.e = rz ? 0 : e;
+    r.s = rz ? 0u : X.s;
     return r;
 }
 
