@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--others", type=int, default=2, help="timed steps for each non-headline algorithm (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--slice-steps", type=int, default=3, help="timed steps of the INT8-slice path (0: skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB device to device (a kernel of known traffic for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -56,6 +60,13 @@ def main():
 
     from paper_1410_1599_amd import inputs as I
     from paper_1410_1599_amd import mp
+
+    if args.copy_probe_mib:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     n, p = args.n, args.prec
     L = p // 32
@@ -130,6 +141,36 @@ def main():
             t = (time.perf_counter() - t0) / args.others
             others[name] = {"ms_per_step": round(t * 1e3, 3), "value": 2.0 * n ** 3 / t}
 
+    # INT8-slice path on the same product (correctly rounded: <= 1/2 ulp)
+    slice_res = None
+    if args.slice_steps > 0:
+        dS = mp.empty(n, n, p)
+        mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
+        torch.cuda.synchronize()
+        mp.mp_profile_read()
+        mp.mp_profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.slice_steps):
+            win = mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / args.slice_steps
+        mp.mp_profile(False)
+        srecs = mp.mp_profile_read()
+        mm = [r for r in srecs if r["kind"] == 2]
+        mm_ms = sum(r["ms"] for r in mm) / max(1, len(mm))
+        mm_tops = mm[0]["units"] / (mm_ms * 1e-3) / 1e12 if mm else 0.0
+        slice_res = {
+            "value": 2.0 * n ** 3 / ts, "unit": "2mln/s", "ms_per_step": round(ts * 1e3, 3),
+            "speedup_vs_limb": round(ms / (ts * 1e3), 3), "windows": list(win),
+            "accuracy": "correctly rounded (<= 0.5 ulp vs the exact product); the limb path's per-operation "
+                        "rounding is never closer",
+            "roofline": {"bound": "mfma", "achieved": round(mm_tops, 2), "peak": 5000.0, "unit": "TOP/s (int8)",
+                         "frac": round(mm_tops / 5000.0, 4), "kernel": "k_slice_gemm (v_mfma_i32_16x16x64_i8)",
+                         "launch_ms": round(mm_ms, 3)},
+            "other_ms": round(sum(r["ms"] for r in srecs if r["kind"] == 3) / args.slice_steps, 3),
+        }
+        del dS
+
     cpu = None
     if not args.no_cpu:
         from oracle import cref
@@ -156,7 +197,7 @@ def main():
         "config": {"workload": "mp_gemm m=l=n=%d prec=%d %s cutoff=%d peel, log-uniform |a| in 2^-21..2^20, "
                                "seeds 6/7" % (n, p, args.algo, args.cutoff),
                    "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
-        "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others,
+        "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others, "slice": slice_res,
     }
     print(json.dumps(out))
 

@@ -149,6 +149,28 @@ int mp_plan_info(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff
                  int *depth, double *n_mul, double *n_addsub, int64_t *ws_bytes, int64_t *n_launches);
 
 /*
+ * INT8-slice product C ~ A B on the matrix cores (an extension beside the
+ * paper's per-operation rounding).  Each row of A is scaled by its largest
+ * exponent e_i and each column of B by its own f_j; every entry becomes an
+ * integer in a window of W = prec + min(spread, extra) bits (spread = the
+ * largest exponent spread among the nonzero entries of a row of A, resp. a
+ * column of B), truncated toward zero; those integers are cut into balanced
+ * signed 8-bit digits, all digit-plane products are exact INT8 MFMA GEMMs with
+ * INT32 accumulation, the exact integer sum is recombined and rounded once to
+ * nearest even:  c_ij = RN(2^(e_i+f_j-W_A-W_B) sum_k trunc(a_ik) trunc(b_kj)).
+ * When every spread is at most `extra` (0..64) nothing is truncated and c_ij is
+ * the correctly rounded exact product (error <= 1/2 ulp).  Otherwise an entry
+ * more than `extra` binades below its row's (column's) largest keeps only the
+ * bits at or above 2^(e_i - W_A) (2^(f_j - W_B)): its truncation error is below
+ * that power of two.  window_out (host, 2 int32, may be NULL) gets
+ * W_A, W_B.  Synchronises the stream (the window depends on the data).
+ */
+int mp_gemm_slice(int64_t m, int64_t l, int64_t n, int prec, int extra,
+                  const uint32_t *A, int64_t lda, int64_t psa,
+                  const uint32_t *B, int64_t ldb, int64_t psb,
+                  uint32_t *C, int64_t ldc, int64_t psc, int32_t *window_out);
+
+/*
  * LU decomposition with partial pivoting of the n x n matrix A in place
  * (Section 4, blocked with panel width K, trailing update A22 := A22 - L21 U12
  * with the product formed by `algo`; the paper's LU does not pivot, this one

@@ -187,6 +187,24 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 
+ProfScope::ProfScope(hipStream_t s, int kind, int op, int L, double units, int64_t ntiles)
+    : s_(s), kind_(kind), op_(op), L_(L), units_(units), ntiles_(ntiles), on_(g_prof_on)
+{
+    if (on_) {
+        (void)hipEventCreate(&e0_);
+        (void)hipEventCreate(&e1_);
+        (void)hipEventRecord(e0_, s_);
+    }
+}
+
+ProfScope::~ProfScope()
+{
+    if (!on_) return;
+    (void)hipEventRecord(e1_, s_);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back(ProfRec{kind_, op_, L_, units_, ntiles_, e0_, e1_});
+}
+
 int run_plan(const Plan& P, Bases bs, hipStream_t s)
 {
     int rc = MP_OK;

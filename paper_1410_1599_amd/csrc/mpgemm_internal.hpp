@@ -20,7 +20,7 @@ int check_prec(int prec, int* L);
 int check_mat(const char* name, const uint32_t* p, int64_t rows, int64_t cols, int64_t ld, int64_t ps);
 bool overlaps(const uint32_t* a, int64_t psa, const uint32_t* b, int64_t psb, int L);
 int device_check();
-enum WsSlot { WS_PLAN = 0, WS_LU = 1 };
+enum WsSlot { WS_PLAN = 0, WS_LU = 1, WS_SLICE = 2, WS_SLICE_EXP = 3 };
 // per-stream, per-slot device buffer of at least `words` uint32 (grown on demand)
 uint32_t* workspace(size_t words, hipStream_t s, int slot, int* rc);
 
@@ -32,5 +32,27 @@ int gemm_internal(int64_t m, int64_t l, int64_t n, int L, int algo, int cutoff, 
 // C := A op B elementwise through a cached one-task plan (no argument checks)
 int ew_internal(int op, int64_t m, int64_t n, int L, const uint32_t* A, int64_t lda, int64_t psa,
                 const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s);
+
+// Records a HIP event pair around the launches of its lifetime on stream s
+// when the step profiler is on (mp_profile); kind 0 = leaf products,
+// 1 = node passes, 2 = INT8 MFMA products, 3 = other slice kernels.
+class ProfScope {
+public:
+    ProfScope(hipStream_t s, int kind, int op, int L, double units, int64_t ntiles);
+    ~ProfScope();
+
+private:
+    hipStream_t s_;
+    int kind_, op_, L_;
+    double units_;
+    int64_t ntiles_;
+    bool on_;
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;
+};
+
+// INT8-slice product (slice.cpp); synchronises the stream
+int slice_internal(int64_t m, int64_t l, int64_t n, int L, int extra, const uint32_t* A, int64_t lda, int64_t psa,
+                   const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc,
+                   int32_t* window_out, hipStream_t s);
 
 }  // namespace mpg

@@ -1,0 +1,150 @@
+// slice.cpp -- host driver of the INT8-slice product and its C-ABI entry.
+//
+// 1. exponent scan: per row of A and column of B, the largest and smallest
+//    exponent of the nonzero entries (read back: the window depends on them);
+// 2. window W = p + min(spread, extra) per operand, S = ceil((W + 2) / 8) digits;
+// 3. digit planes A8[s][i][k], B8[t][j][k] (k contiguous, zero padded);
+// 4. one grouped launch of INT8 MFMA tiles: every diagonal u = s + t, split into
+//    slots whose inner length stays exact in INT32;
+// 5. recombination and one rounding per entry.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "mpgemm_internal.hpp"
+#include "slice.hpp"
+
+using namespace mpg;
+
+namespace {
+
+int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
+
+#define SL_TRY(expr)                                                     \
+    do {                                                                 \
+        hipError_t e_ = (expr);                                          \
+        if (e_ != hipSuccess) {                                          \
+            g_err = std::string("slice path: ") + hipGetErrorString(e_); \
+            return MP_E_DEVICE;                                          \
+        }                                                                \
+    } while (0)
+
+int max_spread(const std::vector<int32_t>& hi, const std::vector<int32_t>& lo)
+{
+    int64_t s = 0;
+    for (size_t i = 0; i < hi.size(); i++)
+        if (hi[i] != INT32_MIN) s = std::max<int64_t>(s, (int64_t)hi[i] - lo[i]);
+    return (int)std::min<int64_t>(s, 1 << 20);
+}
+
+}  // namespace
+
+namespace mpg {
+
+int slice_internal(int64_t m, int64_t l, int64_t n, int L, int extra, const uint32_t* A, int64_t lda, int64_t psa,
+                   const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc,
+                   int32_t* window_out, hipStream_t s)
+{
+    const int p = 32 * L;
+    const int64_t mpad = round_up(m, SLICE_TILE), npad = round_up(n, SLICE_TILE);
+    const int64_t kpad = round_up(std::max<int64_t>(l, 1), SLICE_KSTEP);
+    // scratch: exponent tables (4 arrays), then the digit planes, then G
+    int rc = MP_OK;
+    const size_t exp_words = (size_t)(2 * m + 2 * n + 64);
+    uint32_t* base = workspace(exp_words, s, WS_SLICE_EXP, &rc);
+    if (rc) return rc;
+    int32_t *ea = (int32_t*)base, *ea_lo = ea + m, *fb = ea_lo + m, *fb_lo = fb + n;
+    SL_TRY(launch_slice_scan(L, A, lda, psa, m, l, 0, ea, ea_lo, s));
+    SL_TRY(launch_slice_scan(L, B, ldb, psb, n, l, 1, fb, fb_lo, s));
+    std::vector<int32_t> h(2 * (size_t)m + 2 * (size_t)n);
+    SL_TRY(hipMemcpyAsync(h.data(), base, h.size() * 4, hipMemcpyDeviceToHost, s));
+    SL_TRY(hipStreamSynchronize(s));
+    const std::vector<int32_t> ahi(h.begin(), h.begin() + m), alo(h.begin() + m, h.begin() + 2 * m);
+    const std::vector<int32_t> bhi(h.begin() + 2 * m, h.begin() + 2 * m + n), blo(h.begin() + 2 * m + n, h.end());
+    const int WA = p + std::min(max_spread(ahi, alo), extra);
+    const int WB = p + std::min(max_spread(bhi, blo), extra);
+    if (window_out) {
+        window_out[0] = WA;
+        window_out[1] = WB;
+    }
+    const int SA = (WA + 2 + 7) / 8, SB = (WB + 2 + 7) / 8;
+    const int ndiag = SA + SB - 1;
+    // tasks: diagonal u, pairs split into slots of at most SLICE_KMAX inner length
+    const int64_t pairs_per_slot = std::max<int64_t>(1, SLICE_KMAX / kpad);
+    std::vector<int32_t> slot_begin(1, 0);
+    struct Slot { int u, s0, s1; };
+    std::vector<Slot> slots;
+    for (int u = 0; u < ndiag; u++) {
+        const int lo = std::max(0, u - SB + 1), hi = std::min(u, SA - 1) + 1;
+        for (int s0 = lo; s0 < hi; s0 += (int)pairs_per_slot)
+            slots.push_back(Slot{u, s0, (int)std::min<int64_t>(hi, s0 + pairs_per_slot)});
+        slot_begin.push_back((int32_t)slots.size());
+    }
+    std::vector<SliceTask> tasks;
+    const int ti_n = (int)(mpad / SLICE_TILE), tj_n = (int)(npad / SLICE_TILE);
+    for (size_t q = 0; q < slots.size(); q++)
+        for (int ti = 0; ti < ti_n; ti++)
+            for (int tj = 0; tj < tj_n; tj++)
+                tasks.push_back(SliceTask{slots[q].u, slots[q].s0, slots[q].s1, (int32_t)q, ti, tj});
+    // longest first: the grid drains evenly
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const SliceTask& a, const SliceTask& b) { return (a.s1 - a.s0) > (b.s1 - b.s0); });
+    const int64_t a_plane = mpad * kpad, b_plane = npad * kpad, g_plane = mpad * npad;
+    const size_t bytes_a = (size_t)SA * a_plane, bytes_b = (size_t)SB * b_plane;
+    const size_t bytes_g = (size_t)slots.size() * g_plane * 4;
+    const size_t bytes_t = tasks.size() * sizeof(SliceTask) + slot_begin.size() * 4;
+    const size_t words = (bytes_a + bytes_b + bytes_g + bytes_t) / 4 + 256;
+    uint8_t* ws = (uint8_t*)workspace(words, s, WS_SLICE, &rc);
+    if (rc) return rc;
+    int8_t* A8 = (int8_t*)ws;
+    int8_t* B8 = A8 + ((bytes_a + 255) & ~size_t(255));
+    int32_t* G = (int32_t*)(B8 + ((bytes_b + 255) & ~size_t(255)));
+    SliceTask* d_tasks = (SliceTask*)((uint8_t*)G + bytes_g);
+    int32_t* d_slot_begin = (int32_t*)(d_tasks + tasks.size());
+    SL_TRY(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(SliceTask), hipMemcpyHostToDevice, s));
+    SL_TRY(hipMemcpyAsync(d_slot_begin, slot_begin.data(), slot_begin.size() * 4, hipMemcpyHostToDevice, s));
+    {
+        ProfScope ps(s, 3, 0, L, (double)(m + n) * l, 0);
+        SL_TRY(launch_slice_digits(L, A, lda, psa, m, l, 0, ea, WA, SA, A8, a_plane, mpad, kpad, s));
+        SL_TRY(launch_slice_digits(L, B, ldb, psb, n, l, 1, fb, WB, SB, B8, b_plane, npad, kpad, s));
+    }
+    {
+        // algorithmic INT8 operations: every digit pair over the unpadded product
+        ProfScope ps(s, 2, 0, L, 2.0 * SA * SB * (double)m * (double)l * (double)n, (int64_t)tasks.size());
+        SL_TRY(launch_slice_gemm(d_tasks, (int64_t)tasks.size(), A8, B8, G, a_plane, b_plane, g_plane,
+                                 (int32_t)kpad, (int32_t)npad, s));
+    }
+    {
+        ProfScope ps(s, 3, 1, L, (double)m * n, 0);
+        SL_TRY(launch_slice_combine(L, G, g_plane, (int32_t)npad, d_slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc,
+                                    m, n, s));
+    }
+    // the host vectors above are copied before this call returns only if the
+    // stream has consumed them: wait for the uploads
+    SL_TRY(hipStreamSynchronize(s));
+    return MP_OK;
+}
+
+}  // namespace mpg
+
+extern "C" int mp_gemm_slice(int64_t m, int64_t l, int64_t n, int prec, int extra, const uint32_t* A, int64_t lda,
+                             int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc,
+                             int64_t psc, int32_t* window_out)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if (extra < 0 || extra > SLICE_MAX_EXTRA) return set_err(MP_E_ARG, "extra must be in 0..64");
+    if (m < 0 || l < 0 || n < 0) return set_err(MP_E_ARG, "negative dimension");
+    if ((rc = check_mat("A", A, m, l, lda, psa)) || (rc = check_mat("B", B, l, n, ldb, psb)) ||
+        (rc = check_mat("C", C, m, n, ldc, psc)))
+        return rc;
+    if (m == 0 || n == 0) return MP_OK;
+    if (l > 0 && (overlaps(C, psc, A, psa, L) || overlaps(C, psc, B, psb, L)))
+        return set_err(MP_E_ALIAS, "C overlaps A or B");
+    if ((rc = device_check())) return rc;
+    if ((rc = slice_internal(m, l, n, L, extra, A, lda, psa, B, ldb, psb, C, ldc, psc, window_out, g_stream)))
+        return rc;
+    return device_check();
+}

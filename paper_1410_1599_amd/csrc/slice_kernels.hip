@@ -1,0 +1,352 @@
+// slice_kernels.hip -- the INT8-slice product: MP matrices cut into signed
+// 8-bit digit planes under per-row (A) and per-column (B) exponent scaling,
+// exact INT8 x INT8 -> INT32 products on the matrix cores, recombination in
+// wide integers and one rounding to p bits per entry.
+//
+// With e_i the largest exponent in row i of A and W_A the window width, each
+// a_ik becomes the integer alpha_ik = trunc(a_ik 2^(W_A - e_i)) (exact when
+// e_i - exp(a_ik) <= W_A - p); likewise beta_kj for B with column maxima
+// f_j.  alpha is written in balanced base 256, digits in [-128, 127]:
+// alpha = sum_s d_s 256^s.  Then
+//     sum_k alpha_ik beta_kj = sum_u 256^u G_u,   G_u = sum_{s+t=u} sum_k dA_s dB_t,
+// every G_u is one INT8 GEMM with INT32 accumulation over the concatenated
+// inner index (exact while (pairs x l) 2^14 < 2^31; longer diagonals are
+// split), and c_ij = RN_p(2^(e_i + f_j - W_A - W_B) sum_u 256^u G_u).
+#include "mp_arith.hpp"
+#include "slice.hpp"
+
+namespace mpg {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ exponent scan
+
+// per row (A) or per column (B): largest and smallest exponent of the nonzero
+// entries; a zero row reports max = min = INT32_MIN
+template <int L>
+__global__ void __launch_bounds__(256)
+k_slice_scan(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer, int64_t inner, int by_cols,
+             int32_t* __restrict__ emax, int32_t* __restrict__ emin)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= outer) return;
+    int32_t hi = INT32_MIN, lo = INT32_MAX;
+    for (int64_t q = 0; q < inner; q++) {
+        const int64_t idx = by_cols ? q * ld + o : o * ld + q;
+        if (X[(L - 1) * ps + idx] == 0) continue;
+        const int32_t e = (int32_t)X[L * ps + idx];
+        hi = e > hi ? e : hi;
+        lo = e < lo ? e : lo;
+    }
+    emax[o] = hi;
+    emin[o] = hi == INT32_MIN ? INT32_MIN : lo;
+}
+
+// ------------------------------------------------------------------ slicing
+
+// word w (bits 32w .. 32w+31) of M * 2^sh, M the L-limb mantissa, sh of any
+// sign (bits shifted below 0 are dropped: truncation toward zero)
+template <int L>
+__device__ __forceinline__ uint32_t shifted_word(const uint32_t* m, int32_t sh, int w)
+{
+    const int32_t pos = 32 * w - sh;                 // bit of M at bit 32w of the result
+    const int32_t q = pos >> 5;                      // arithmetic: floor
+    const uint32_t r = (uint32_t)pos & 31u;
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+        lo = (q == k) ? m[k] : lo;
+        hi = (q + 1 == k) ? m[k] : hi;
+    }
+    return r ? funnel(hi, lo, r) : lo;
+}
+
+// one thread: 4 consecutive inner indices (k) of one outer index (row of A /
+// column of B); writes digit plane s at D[s * dps + outer * kpad + k]
+template <int L, int NW>
+__global__ void __launch_bounds__(256)
+k_slice_digits(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer, int64_t inner, int by_cols,
+               const int32_t* __restrict__ emax, int32_t W, int32_t S, int8_t* __restrict__ D, int64_t dps,
+               int64_t outer_pad, int64_t kpad)
+{
+    const int64_t gidx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t ngroups = kpad >> 2;
+    // B (by_cols): consecutive threads take consecutive outer indices so the reads coalesce
+    int64_t o, g;
+    if (by_cols) {
+        o = gidx % outer_pad;
+        g = gidx / outer_pad;
+    } else {
+        g = gidx % ngroups;
+        o = gidx / ngroups;
+    }
+    if (o >= outer_pad || g >= ngroups) return;
+    uint32_t dig[4][NW];                             // balanced digits, 4 per word
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const int64_t k = 4 * g + e;
+        uint32_t m[L];
+        uint32_t sgn = 0;
+        int32_t ex = 0;
+        bool nz = false;
+        if (o < outer && k < inner) {
+            const int64_t idx = by_cols ? k * ld + o : o * ld + k;
+#pragma unroll
+            for (int q = 0; q < L; q++) m[q] = X[q * ps + idx];
+            ex = (int32_t)X[L * ps + idx];
+            sgn = X[(L + 1) * ps + idx];
+            nz = m[L - 1] != 0;
+        }
+        if (!nz) {
+#pragma unroll
+            for (int q = 0; q < L; q++) m[q] = 0;
+            sgn = 0;
+        }
+        // alpha = M * 2^(e - p) * 2^(W - emax) = M * 2^sh
+        const int32_t sh = nz ? (W - 32 * L - (emax[o] - ex)) : 0;
+        // two's complement of +-alpha, word by word, then balanced base-256 recoding
+        uint32_t neg_c = sgn;                        // +1 of the negation
+        int32_t rc = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            uint32_t a = shifted_word<L>(m, sh, w);
+            if (sgn) a = addc(~a, 0u, neg_c, &neg_c);
+            uint32_t out = 0;
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                int32_t v = (int32_t)((a >> (8 * b)) & 0xffu) + rc;
+                rc = v >= 128 ? 1 : 0;
+                v -= rc ? 256 : 0;
+                out |= ((uint32_t)v & 0xffu) << (8 * b);
+            }
+            dig[e][w] = out;
+        }
+    }
+    // digit plane s, 4 consecutive k in one dword
+    for (int s = 0; s < S; s++) {
+        const int w = s >> 2, b = s & 3;
+        uint32_t v = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int q = 0; q < NW; q++) x = (q == w) ? dig[e][q] : x;
+            v |= ((x >> (8 * b)) & 0xffu) << (8 * e);
+        }
+        *(uint32_t*)(D + (int64_t)s * dps + o * kpad + 4 * g) = v;
+    }
+}
+
+// ------------------------------------------------------------------ INT8 products
+
+constexpr int TM = 128, TN = 128, TKK = 64, LDSW = TKK + 16;
+
+// one workgroup: a 128 x 128 tile of G_slot = sum_{s = s0}^{s1 - 1} A8_s B8_{u-s}^T
+__global__ void __launch_bounds__(256)
+k_slice_gemm(const SliceTask* __restrict__ tasks, const int8_t* __restrict__ A8, const int8_t* __restrict__ B8,
+             int32_t* __restrict__ G, int64_t a_plane, int64_t b_plane, int64_t g_plane, int32_t kpad,
+             int32_t npad)
+{
+    __shared__ __attribute__((aligned(16))) int8_t sA[TM][LDSW];
+    __shared__ __attribute__((aligned(16))) int8_t sB[TN][LDSW];
+    const SliceTask T = tasks[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    v4i acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = (v4i){0, 0, 0, 0};
+    const int64_t i0 = (int64_t)T.ti * TM, j0 = (int64_t)T.tj * TN;
+    for (int s = T.s0; s < T.s1; s++) {
+        const int8_t* Ap = A8 + (int64_t)s * a_plane + i0 * kpad;
+        const int8_t* Bp = B8 + (int64_t)(T.u - s) * b_plane + j0 * kpad;
+        for (int k0 = 0; k0 < kpad; k0 += TKK) {
+            __syncthreads();
+            for (int c = tid; c < TM * TKK / 16; c += 256) {
+                const int r = c >> 2, q = c & 3;
+                *(v4i*)&sA[r][q * 16] = *(const v4i*)(Ap + (int64_t)r * kpad + k0 + q * 16);
+                *(v4i*)&sB[r][q * 16] = *(const v4i*)(Bp + (int64_t)r * kpad + k0 + q * 16);
+            }
+            __syncthreads();
+            v4i af[4], bf[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                af[t] = *(const v4i*)&sA[wy * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
+                bf[t] = *(const v4i*)&sB[wx * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    int32_t* Gp = G + (int64_t)T.slot * g_plane;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int64_t row = i0 + wy * 64 + a * 16 + 4 * (lane >> 4) + e;
+                const int64_t col = j0 + wx * 64 + b * 16 + (lane & 15);
+                Gp[row * npad + col] = acc[a][b][e];
+            }
+}
+
+// ------------------------------------------------------------------ recombination
+
+// c_ij = RN_p(2^(e_i + f_j - W_A - W_B) * sum_u 256^u G_u,ij).  slot_begin[u] ..
+// slot_begin[u+1] are the G slots of diagonal u.  The sum is kept as signed
+// 64-bit partial sums per 32-bit position (each below 2^58), carried once.
+template <int L, int NWZ>
+__global__ void __launch_bounds__(256)
+k_slice_combine(const int32_t* __restrict__ G, int64_t g_plane, int32_t npad, const int32_t* __restrict__ slot_begin,
+                int32_t ndiag, const int32_t* __restrict__ ea, const int32_t* __restrict__ fb, int32_t WA, int32_t WB,
+                uint32_t* __restrict__ C, int64_t ldc, int64_t psc, int64_t m, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= m * n) return;
+    const int64_t i = e / n, j = e % n;
+    int64_t acc[NWZ];
+#pragma unroll
+    for (int q = 0; q < NWZ; q++) acc[q] = 0;
+#pragma unroll
+    for (int q = 0; q < NWZ; q++) {
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int u = 4 * q + b;
+            if (u >= ndiag) break;
+            for (int sl = slot_begin[u]; sl < slot_begin[u + 1]; sl++)
+                acc[q] += (int64_t)G[(int64_t)sl * g_plane + i * npad + j] * ((int64_t)1 << (8 * b));
+        }
+    }
+    // carry into two's complement limbs
+    uint32_t Z[NWZ];
+    int64_t cy = 0;
+#pragma unroll
+    for (int q = 0; q < NWZ; q++) {
+        const int64_t t = acc[q] + cy;
+        Z[q] = (uint32_t)t;
+        cy = t >> 32;
+    }
+    const bool neg = cy < 0;
+    if (neg) {
+        uint32_t c = 1;
+#pragma unroll
+        for (int q = 0; q < NWZ; q++) Z[q] = addc(~Z[q], 0u, c, &c);
+    }
+    // bit length
+    int32_t top = -1;
+#pragma unroll
+    for (int q = 0; q < NWZ; q++) top = Z[q] ? q : top;
+    MP<L> r = mp_zero<L>();
+    if (top >= 0) {
+        uint32_t tw = 0;
+#pragma unroll
+        for (int q = 0; q < NWZ; q++) tw = (q == top) ? Z[q] : tw;
+        const int32_t b = 32 * top + 32 - (int32_t)__builtin_clz(tw);    // bit length of |Z|
+        // keep bits [b - p, b): shift right by sh = b - p (may be negative)
+        const int32_t sh = b - 32 * L;
+        uint32_t M[L];
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const int32_t pos = sh + 32 * k;
+            const int32_t q = pos >> 5;
+            const uint32_t rr = (uint32_t)pos & 31u;
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int t = 0; t < NWZ; t++) {
+                lo = (q == t) ? Z[t] : lo;
+                hi = (q + 1 == t) ? Z[t] : hi;
+            }
+            M[k] = rr ? funnel(hi, lo, rr) : lo;
+        }
+        uint32_t rb = 0, st = 0;
+        if (sh > 0) {
+            const int32_t rpos = sh - 1;             // round bit position in Z
+#pragma unroll
+            for (int t = 0; t < NWZ; t++) {
+                const int32_t base = 32 * t;
+                if (rpos >= base && rpos < base + 32) {
+                    rb = (Z[t] >> (rpos - base)) & 1u;
+                    st |= Z[t] & ((1u << (rpos - base)) - 1u);
+                } else if (base + 32 <= rpos) {
+                    st |= Z[t];
+                }
+            }
+        }
+        uint32_t cu = rb & ((st != 0) | (M[0] & 1u));
+#pragma unroll
+        for (int k = 0; k < L; k++) r.m[k] = addc(M[k], 0u, cu, &cu);
+        int32_t ex = b + (ea[i] + fb[j] - WA - WB);
+        if (cu) {
+            r.m[L - 1] = 0x80000000u;
+            ex += 1;
+        }
+        r.e = ex;
+        r.s = neg ? 1u : 0u;
+    }
+    store<L>(C, psc, i * ldc + j, r);
+}
+
+}  // namespace
+
+hipError_t launch_slice_scan(int L, const uint32_t* X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
+                             int by_cols, int32_t* emax, int32_t* emin, hipStream_t s)
+{
+    if (outer <= 0) return hipSuccess;
+    const dim3 g((unsigned)((outer + 255) / 256));
+    switch (L) {
+    case 4: hipLaunchKernelGGL((k_slice_scan<4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, emin); break;
+    case 8: hipLaunchKernelGGL((k_slice_scan<8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, emin); break;
+    case 16: hipLaunchKernelGGL((k_slice_scan<16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, emin); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_digits(int L, const uint32_t* X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
+                               int by_cols, const int32_t* emax, int32_t W, int32_t S, int8_t* D, int64_t dps,
+                               int64_t outer_pad, int64_t kpad, hipStream_t s)
+{
+    const int64_t threads = outer_pad * (kpad / 4);
+    const dim3 g((unsigned)((threads + 255) / 256));
+    // NW = words of the W-bit window plus the recoding headroom, per precision
+    switch (L) {
+    case 4: hipLaunchKernelGGL((k_slice_digits<4, SLICE_NW4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
+    case 8: hipLaunchKernelGGL((k_slice_digits<8, SLICE_NW8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
+    case 16: hipLaunchKernelGGL((k_slice_digits<16, SLICE_NW16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_gemm(const SliceTask* tasks, int64_t ntasks, const int8_t* A8, const int8_t* B8, int32_t* G,
+                             int64_t a_plane, int64_t b_plane, int64_t g_plane, int32_t kpad, int32_t npad,
+                             hipStream_t s)
+{
+    if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slice_gemm, dim3((unsigned)ntasks), dim3(256), 0, s, tasks, A8, B8, G, a_plane, b_plane,
+                       g_plane, kpad, npad);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_combine(int L, const int32_t* G, int64_t g_plane, int32_t npad, const int32_t* slot_begin,
+                                int32_t ndiag, const int32_t* ea, const int32_t* fb, int32_t WA, int32_t WB,
+                                uint32_t* C, int64_t ldc, int64_t psc, int64_t m, int64_t n, hipStream_t s)
+{
+    const dim3 g((unsigned)((m * n + 255) / 256));
+    switch (L) {
+    case 4: hipLaunchKernelGGL((k_slice_combine<4, SLICE_NWZ4>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
+    case 8: hipLaunchKernelGGL((k_slice_combine<8, SLICE_NWZ8>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
+    case 16: hipLaunchKernelGGL((k_slice_combine<16, SLICE_NWZ16>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mpg

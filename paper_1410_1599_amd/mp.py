@@ -55,6 +55,7 @@ def _load():
         "mp_lu_solve": ([i64, i32, vp, i64, i64, vp, vp, i64], i32),
         "mp_release_workspace": ([], i32),
         "mp_profile": ([i32], i32),
+        "mp_gemm_slice": ([i64, i64, i64, i32, i32] + mat * 3 + [i32p], i32),
         "mp_profile_read": ([i32, i32p, i32p, i32p, dp, i64p, ctypes.POINTER(ctypes.c_float)], i32),
     }
     for name, (args, res) in sig.items():
@@ -186,6 +187,14 @@ def mp_lu_solve(n, prec, LU, piv, b):
     pa, lda, psa = _mat(LU)
     pb, _, psb = _mat(b)
     return _check(lib.mp_lu_solve(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()), pb, psb))
+
+
+def mp_gemm_slice(m, l, n, prec, extra, A, B, C):
+    """INT8-slice product; returns the windows (W_A, W_B) it used."""
+    mp_set_stream()
+    w = (ctypes.c_int * 2)()
+    _check(lib.mp_gemm_slice(m, l, n, prec, int(extra), *_mat(A), *_mat(B), *_mat(C), w))
+    return w[0], w[1]
 
 
 def mp_release_workspace():

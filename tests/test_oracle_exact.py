@@ -34,3 +34,32 @@ def test_ulp_error_of_neighbours():
     up = (x[0] + 1, 0)
     assert exact.ulp_error(up, n, f, p) == 1
     assert exact.ulp_error(mpnum.ZERO, 0, 0, p) == 0
+
+
+def test_slice_model_equals_exact_rounding_when_window_covers_spread():
+    p = 128
+    A = I.from_planes(I.log_uniform(4, 30, p, 3, -6, 6), p)
+    B = I.from_planes(I.log_uniform(30, 5, p, 4, -6, 6), p)
+    WA, WB = exact.window_widths(A, B, p, 64)
+    assert WA <= p + 12 and WB <= p + 12
+    for i in range(4):
+        for j in range(5):
+            assert exact.slice_model_entry(A, B, i, j, p, WA, WB) == exact.exact_entry(A, B, i, j, p)
+
+
+def test_slice_model_truncates_toward_zero_below_the_window():
+    # p = 32 (model only): row max 2^0; with W = p + 2 an entry 2^-40 below
+    # keeps nothing, one 3 binades below keeps its top 31 bits, truncated
+    p = 32
+    big = (1 << 31, 1)                    # 1.0
+    tiny = ((1 << 31) | 1, -40)           # about 2^-41
+    mid = (-((1 << 31) | 5), -2)          # about -2^-3, low bits set
+    one = (1 << 31, 1)
+    A = [[big, tiny, mid]]
+    B = [[one], [one], [one]]
+    got = exact.slice_model_entry(A, B, 0, 0, p, p + 2, p)
+    # alpha = trunc(a * 2^(W - 1)) = trunc(a * 2^33)
+    alpha = [(1 << 33), 0, -(((1 << 31) | 5) >> 1)]   # shift W - p - 3 = -1
+    z = sum(alpha) * (1 << 31)            # beta = 2^31 for 1.0 with W_B = p, f = 1
+    assert got == mpnum.rn(z, 1 + 1 - (p + 2) - p, p)
+    assert exact.window_widths(A, B, p, 2) == (p + 2, p)
