@@ -62,7 +62,10 @@ enum mp_algo {
     MP_SIMPLE = 0,    /* eq. (1): c_ij = sum_k a_ik b_kj, k ascending from exact 0 */
     MP_BLOCK = 1,     /* eq. (2): LDS-staged tiles, same per-element order as Simple (bit-identical) */
     MP_STRASSEN = 2,  /* Section 2: P1..P7 and the C quadrants, recursing above the cutoff */
-    MP_WINOGRAD = 3   /* Section 2: Winograd's variant S1..S8, M1..M7, T1, T2 */
+    MP_WINOGRAD = 3,  /* Section 2: Winograd's variant S1..S8, M1..M7, T1, T2 */
+    MP_AUTO = 4       /* the autotuner's choice for the shape and precision (mp_tune), else
+                         MP_WINOGRAD with cutoff 64 when min(m, l, n) > 64 and MP_SIMPLE below;
+                         mp_auto_choice reports which, so the result can be reproduced */
 };
 
 enum mp_policy {      /* odd dimensions above the cutoff (Section 2, last paragraph) */
@@ -188,6 +191,14 @@ int mp_lu_ex(int64_t n, int prec, uint32_t *A, int64_t lda, int64_t psa, int32_t
              int panel, int algo, int cutoff, int policy);
 
 /*
+ * mp_lu_ex without waiting: info is written to the device int32 *info_dev and
+ * nothing synchronises (for request loops that overlap several factorisations
+ * on different streams).
+ */
+int mp_lu_async(int64_t n, int prec, uint32_t *A, int64_t lda, int64_t psa, int32_t *piv, int32_t *info_dev,
+                int panel, int algo, int cutoff, int policy);
+
+/*
  * Solve A x = b from the factors of mp_lu: the row swaps of piv in order,
  * forward substitution with the unit lower factor, back substitution with the
  * upper factor (true quotients by the diagonal).  b (n x 1, plane stride psb)
@@ -209,7 +220,33 @@ int mp_lu_solve(int64_t n, int prec, const uint32_t *LU, int64_t lda, int64_t ps
 int mp_profile(int enable);
 int mp_profile_read(int max, int *kind, int *op, int *L, double *units, int64_t *ntiles, float *ms);
 
-/* Free the workspaces and cached plans of the current device (synchronises the device). */
+/*
+ * Graph mode (process-wide, default off): each mp_gemm / mp_add-style call
+ * captures its grouped launches into a hipGraph the first time a given plan
+ * runs with given operand pointers on a given non-null stream, and replays the
+ * graph afterwards (no per-launch host cost).  Calls on the null stream launch
+ * directly.  Graphs are freed by mp_release_workspace.
+ */
+int mp_set_graph_mode(int enable);
+
+/*
+ * Autotuner.  mp_tune times Simple, Block, and Strassen / Winograd with cutoffs
+ * 32, 64, 128, 256 (below min(m, l, n)) and both leaf kernels on library-owned
+ * scratch operands of the given shape (uniform (-1, 1) values), `reps` runs
+ * each on the calling thread's stream, and records the fastest for
+ * (prec, ceil(log2 m), ceil(log2 l), ceil(log2 n)).  Outputs (host, may be
+ * NULL): the choice and its milliseconds.  Synchronises the stream.
+ * mp_auto_choice reports what MP_AUTO would use.  mp_tune_save writes the
+ * table as JSON; mp_tune_load reads such a file and returns the entries read
+ * (negative on error).  Different choices give different (each correctly
+ * rounded per operation) results.
+ */
+int mp_tune(int64_t m, int64_t l, int64_t n, int prec, int reps, int *algo, int *cutoff, int *leaf, float *ms);
+int mp_auto_choice(int64_t m, int64_t l, int64_t n, int prec, int *algo, int *cutoff, int *leaf);
+int mp_tune_save(const char *path);
+int mp_tune_load(const char *path);
+
+/* Free the workspaces, captured graphs and cached plans of the current device (synchronises the device). */
 int mp_release_workspace(void);
 
 #ifdef __cplusplus

@@ -8,6 +8,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <array>
+#include <cstdio>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -31,11 +33,34 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+struct GraphKey {
+    const Plan* plan;
+    uint32_t* p[NBASES];
+    hipStream_t s;
+    bool operator<(const GraphKey& o) const
+    {
+        if (plan != o.plan) return plan < o.plan;
+        for (int i = 0; i < NBASES; i++)
+            if (p[i] != o.p[i]) return p[i] < o.p[i];
+        return s < o.s;
+    }
+};
+
+struct TuneEntry {
+    int algo, cutoff, leaf;
+    float ms;
+};
+
 struct DeviceState {
     std::mutex mu;
     std::unordered_map<PlanKey, std::unique_ptr<Plan>, PlanKeyHash> plans;
     std::map<std::pair<hipStream_t, int>, DevBuf> ws;     // per stream and slot
+    std::map<GraphKey, hipGraphExec_t> graphs;            // captured plans (graph mode)
 };
+
+std::mutex g_tune_mu;
+std::map<std::array<int64_t, 4>, TuneEntry> g_tune;      // (prec, m, l, n bucket) -> choice
+int g_graph_mode = 0;
 
 std::mutex g_dev_mu;
 std::map<int, std::unique_ptr<DeviceState>> g_dev;
@@ -185,10 +210,11 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+thread_local bool g_capturing = false;
 std::vector<ProfRec> g_prof;
 
 ProfScope::ProfScope(hipStream_t s, int kind, int op, int L, double units, int64_t ntiles)
-    : s_(s), kind_(kind), op_(op), L_(L), units_(units), ntiles_(ntiles), on_(g_prof_on)
+    : s_(s), kind_(kind), op_(op), L_(L), units_(units), ntiles_(ntiles), on_(g_prof_on && !g_capturing)
 {
     if (on_) {
         (void)hipEventCreate(&e0_);
@@ -205,16 +231,54 @@ ProfScope::~ProfScope()
     g_prof.push_back(ProfRec{kind_, op_, L_, units_, ntiles_, e0_, e1_});
 }
 
+int launch_steps(const Plan& P, const Bases& bs, hipStream_t s);
+
+// Graph mode: the first call of a plan with given operand pointers and stream
+// captures its launches into a hipGraph; later calls replay it.  The null
+// stream cannot be captured: calls on it launch directly.
 int run_plan(const Plan& P, Bases bs, hipStream_t s)
 {
     int rc = MP_OK;
     bs.p[BASE_WS] = workspace((size_t)P.ws_words, s, WS_PLAN, &rc);
     if (rc) return rc;
+    if (!g_graph_mode || s == nullptr) return launch_steps(P, bs, s);
+    DeviceState& S = dev_state();
+    GraphKey key{&P, {bs.p[0], bs.p[1], bs.p[2], bs.p[3]}, s};
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> g(S.mu);
+        auto it = S.graphs.find(key);
+        if (it != S.graphs.end()) exec = it->second;
+    }
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return set_err(MP_E_DEVICE, "stream capture failed to start");
+        g_capturing = true;                    // no event records inside a capture
+        rc = launch_steps(P, bs, s);
+        g_capturing = false;
+        const hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc) return rc;
+        if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return set_err(MP_E_DEVICE, "graph capture failed");
+        }
+        (void)hipGraphDestroy(graph);
+        std::lock_guard<std::mutex> g(S.mu);
+        S.graphs[key] = exec;
+    }
+    ProfScope ps(s, 4, 0, P.key.L, P.n_mul, 0);
+    if (hipGraphLaunch(exec, s) != hipSuccess) return set_err(MP_E_DEVICE, "graph launch failed");
+    return MP_OK;
+}
+
+int launch_steps(const Plan& P, const Bases& bs, hipStream_t s)
+{
     // the tile map holds indices into the plan's whole task arrays
     for (const Step& st : P.steps) {
         hipError_t e;
         ProfRec pr{};
-        const bool prof = g_prof_on;
+        const bool prof = g_prof_on && !g_capturing;
         if (prof) {
             pr = ProfRec{st.kind, st.op, P.key.L, st.units, st.ntiles, nullptr, nullptr};
             (void)hipEventCreate(&pr.e0);
@@ -300,6 +364,31 @@ int ew_internal(int op, int64_t m, int64_t n, int L, const uint32_t* A, int64_t 
     return run_plan(*P, bs, s);
 }
 
+// ---- autotuner: times candidate (algorithm, cutoff, leaf kernel) choices
+// for a shape and precision on library-owned scratch operands and remembers
+// the fastest per (prec, power-of-two bucket of m, l, n)
+std::array<int64_t, 4> tune_key(int64_t m, int64_t l, int64_t n, int prec)
+{
+    auto b = [](int64_t v) { int64_t c = 0; while ((int64_t(1) << c) < v) c++; return c; };
+    return {prec, b(m), b(l), b(n)};
+}
+
+bool tune_lookup(int64_t m, int64_t l, int64_t n, int prec, TuneEntry* out)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_key(m, l, n, prec));
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+// default when nothing was tuned: Winograd down to 64 (Simple below)
+TuneEntry tune_default(int64_t m, int64_t l, int64_t n)
+{
+    if (std::min(m, std::min(l, n)) > 64) return TuneEntry{ALGO_WINOGRAD, 64, LEAF_SIMPLE, 0.f};
+    return TuneEntry{ALGO_SIMPLE, 0, LEAF_SIMPLE, 0.f};
+}
+
 int g_leaf = LEAF_SIMPLE;
 int g_policy = POLICY_PEEL;
 
@@ -340,11 +429,18 @@ int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, 
 {
     int L, rc;
     if ((rc = check_prec(prec, &L))) return rc;
-    if (algo < ALGO_SIMPLE || algo > ALGO_WINOGRAD) return set_err(MP_E_ARG, "unknown algorithm");
+    if (algo < ALGO_SIMPLE || algo > ALGO_AUTO) return set_err(MP_E_ARG, "unknown algorithm");
     if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
     if (policy < POLICY_PEEL || policy > POLICY_MIXED) return set_err(MP_E_ARG, "unknown odd-size policy");
     if (leaf != LEAF_SIMPLE && leaf != LEAF_BLOCK) return set_err(MP_E_ARG, "unknown leaf kernel");
     if (m < 0 || l < 0 || n < 0) return set_err(MP_E_ARG, "negative dimension");
+    if (algo == ALGO_AUTO) {
+        TuneEntry t;
+        if (!tune_lookup(m, l, n, prec, &t)) t = tune_default(m, l, n);
+        algo = t.algo;
+        cutoff = t.cutoff;
+        leaf = t.leaf;
+    }
     if ((rc = check_mat("A", A, m, l, lda, psa)) || (rc = check_mat("B", B, l, n, ldb, psb)) ||
         (rc = check_mat("C", C, m, n, ldc, psc)))
         return rc;
@@ -449,6 +545,129 @@ int mp_profile_read(int max, int* kind, int* op, int* L, double* units, int64_t*
     return n;
 }
 
+int mp_set_graph_mode(int enable)
+{
+    g_graph_mode = enable ? 1 : 0;
+    return MP_OK;
+}
+
+int mp_auto_choice(int64_t m, int64_t l, int64_t n, int prec, int* algo, int* cutoff, int* leaf)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    TuneEntry t;
+    if (!tune_lookup(m, l, n, prec, &t)) t = tune_default(m, l, n);
+    if (algo) *algo = t.algo;
+    if (cutoff) *cutoff = t.cutoff;
+    if (leaf) *leaf = t.leaf;
+    return MP_OK;
+}
+
+int mp_tune(int64_t m, int64_t l, int64_t n, int prec, int reps, int* algo, int* cutoff, int* leaf, float* ms)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if (m < 1 || l < 1 || n < 1 || m > INT32_MAX || l > INT32_MAX || n > INT32_MAX)
+        return set_err(MP_E_ARG, "dimensions must be in 1 .. 2^31 - 1");
+    if ((rc = device_check())) return rc;
+    reps = reps < 1 ? 1 : reps;
+    hipStream_t s = g_stream;
+    const size_t wa = (size_t)(L + 2) * m * l, wb = (size_t)(L + 2) * l * n, wc = (size_t)(L + 2) * m * n;
+    uint32_t* buf = nullptr;
+    if (hipMalloc(&buf, 4 * (wa + wb + wc)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(MP_E_NOMEM, "tuner scratch allocation failed");
+    }
+    uint32_t *A = buf, *B = buf + wa, *C = buf + wa + wb;
+    if (launch_fill_uniform(L, A, m * l, m * l, 12345u, s) != hipSuccess ||
+        launch_fill_uniform(L, B, l * n, l * n, 67890u, s) != hipSuccess) {
+        (void)hipFree(buf);
+        return set_err(MP_E_DEVICE, "tuner fill failed");
+    }
+    std::vector<TuneEntry> cand = {{ALGO_SIMPLE, 0, LEAF_SIMPLE, 0.f}, {ALGO_BLOCK, 0, LEAF_BLOCK, 0.f}};
+    const int64_t mn = std::min(m, std::min(l, n));
+    for (int a : {ALGO_WINOGRAD, ALGO_STRASSEN})
+        for (int c : {32, 64, 128, 256})
+            if (mn > c)
+                for (int lf : {LEAF_SIMPLE, LEAF_BLOCK}) cand.push_back(TuneEntry{a, c, lf, 0.f});
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    TuneEntry best{ALGO_SIMPLE, 0, LEAF_SIMPLE, 1e30f};
+    for (TuneEntry& t : cand) {
+        rc = gemm_internal(m, l, n, L, t.algo, t.cutoff, POLICY_PEEL, t.leaf, A, l, m * l, B, n, l * n, C, n, m * n, s);
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !rc; r++)
+            rc = gemm_internal(m, l, n, L, t.algo, t.cutoff, POLICY_PEEL, t.leaf, A, l, m * l, B, n, l * n, C, n,
+                               m * n, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float t_ms = 0;
+        (void)hipEventElapsedTime(&t_ms, e0, e1);
+        t.ms = t_ms / reps;
+        if (t.ms < best.ms) best = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[tune_key(m, l, n, prec)] = best;
+    }
+    if (algo) *algo = best.algo;
+    if (cutoff) *cutoff = best.cutoff;
+    if (leaf) *leaf = best.leaf;
+    if (ms) *ms = best.ms;
+    return device_check();
+}
+
+int mp_tune_save(const char* path)
+{
+    if (!path) return set_err(MP_E_ARG, "path is NULL");
+    FILE* f = fopen(path, "w");
+    if (!f) return set_err(MP_E_ARG, "cannot open the tuning file");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    fprintf(f, "[");
+    bool first = true;
+    for (auto& kv : g_tune) {
+        fprintf(f, "%s\n {\"prec\": %lld, \"m_log2\": %lld, \"l_log2\": %lld, \"n_log2\": %lld, \"algo\": %d, "
+                   "\"cutoff\": %d, \"leaf\": %d, \"ms\": %.4f}",
+                first ? "" : ",", (long long)kv.first[0], (long long)kv.first[1], (long long)kv.first[2],
+                (long long)kv.first[3], kv.second.algo, kv.second.cutoff, kv.second.leaf, kv.second.ms);
+        first = false;
+    }
+    fprintf(f, "\n]\n");
+    fclose(f);
+    return MP_OK;
+}
+
+int mp_tune_load(const char* path)
+{
+    if (!path) return set_err(MP_E_ARG, "path is NULL");
+    FILE* f = fopen(path, "r");
+    if (!f) return set_err(MP_E_ARG, "cannot open the tuning file");
+    long long pr, a, b, c;
+    int al, cu, lf;
+    float t;
+    int got = 0;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        if (sscanf(line, " {\"prec\": %lld, \"m_log2\": %lld, \"l_log2\": %lld, \"n_log2\": %lld, \"algo\": %d, "
+                         "\"cutoff\": %d, \"leaf\": %d, \"ms\": %f}",
+                   &pr, &a, &b, &c, &al, &cu, &lf, &t) == 8) {
+            if (al < ALGO_SIMPLE || al > ALGO_WINOGRAD || lf < 0 || lf > 1 || cu < 0) continue;
+            g_tune[{pr, a, b, c}] = TuneEntry{al, cu, lf, t};
+            got++;
+        }
+    }
+    fclose(f);
+    return got;
+}
+
 int mp_release_workspace(void)
 {
     DeviceState& S = dev_state();
@@ -457,6 +676,8 @@ int mp_release_workspace(void)
     for (auto& kv : S.ws)
         if (kv.second.p) (void)hipFree(kv.second.p);
     S.ws.clear();
+    for (auto& kv : S.graphs) (void)hipGraphExecDestroy(kv.second);
+    S.graphs.clear();
     for (auto& kv : S.plans) free_plan_device(*kv.second);
     S.plans.clear();
     return MP_OK;

@@ -222,7 +222,57 @@ k_node(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile_task
     }
 }
 
+// ------------------------------------------------------------------ scratch fill
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_fill_uniform(uint32_t* X, int64_t ps, int64_t count, uint32_t seed)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t h = mix32(seed ^ mix32((uint32_t)i ^ mix32((uint32_t)(i >> 32))));
+#pragma unroll
+    for (int k = 0; k < L; k++) X[k * ps + i] = mix32(h + 0x9e3779b9u * (k + 1));
+    X[(L - 1) * ps + i] |= 0x80000000u;
+    X[L * ps + i] = (uint32_t)(-(int32_t)(h & 3));
+    X[(L + 1) * ps + i] = (h >> 2) & 1;
+}
+
 // ------------------------------------------------------------------ launchers
+
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t* X, int64_t count, int32_t value)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) X[i] = value;
+}
+
+hipError_t launch_fill_i32(int32_t* X, int64_t count, int32_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, X, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ps, int64_t count, uint32_t seed, hipStream_t s)
+{
+    const dim3 g((unsigned)((count + 255) / 256));
+    switch (L) {
+    case 4: hipLaunchKernelGGL((k_fill_uniform<4>), g, dim3(256), 0, s, X, ps, count, seed); break;
+    case 8: hipLaunchKernelGGL((k_fill_uniform<8>), g, dim3(256), 0, s, X, ps, count, seed); break;
+    case 16: hipLaunchKernelGGL((k_fill_uniform<16>), g, dim3(256), 0, s, X, ps, count, seed); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 template <int L>
 static hipError_t gemm_launch_L(int kind, const GemmTask* tasks, const int32_t* tile_task, int64_t ntiles,

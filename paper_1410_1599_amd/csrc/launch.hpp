@@ -21,9 +21,22 @@ hipError_t launch_gemm(int L, int kind, const GemmTask* tasks, const int32_t* ti
 hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,
                        const Bases& bs, int64_t grid, hipStream_t s);
 
+// n elements of uniformly distributed p-bit values in (-1, 1) (scratch data
+// of the autotuner; a hash of seed, index and limb)
+hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ps, int64_t count, uint32_t seed, hipStream_t s);
+
+// X[0 .. count) = value (int32); used instead of a memset so captured
+// sequences hold kernels only
+hipError_t launch_fill_i32(int32_t* X, int64_t count, int32_t value, hipStream_t s);
+
 // LU building blocks (lu_kernels.hip); the matrix is one MatRef on base A
 hipError_t launch_lu_pivot(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int32_t* piv, int32_t* info,
                            hipStream_t s);
+hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                                int32_t* piv, int32_t* info, hipStream_t s);
+hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, hipStream_t s);
+hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t kb, int64_t je, int64_t n,
+                         hipStream_t s);
 hipError_t launch_lu_swap(int L, const Bases& bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0,
                           int64_t col1, hipStream_t s);
 hipError_t launch_lu_scale(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, hipStream_t s);

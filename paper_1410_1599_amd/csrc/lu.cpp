@@ -28,8 +28,10 @@ namespace {
         }                                                                \
     } while (0)
 
-int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info_host, int panel,
-           int algo, int cutoff, int policy, hipStream_t s)
+// info_dev: device int32 that receives info (the first zero pivot + 1, or 0);
+// with info_host non-NULL the stream is synchronised and info copied there
+int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info_host,
+           int32_t* info_dev, int panel, int algo, int cutoff, int policy, hipStream_t s)
 {
     int rc = MP_OK;
     const int64_t m2max = n > panel ? n - panel : 0;
@@ -37,8 +39,8 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
     // aux buffer: the trailing product P, then one int32 status word
     uint32_t* aux = workspace(pwords + 64, s, WS_LU, &rc);
     if (rc) return rc;
-    int32_t* status = (int32_t*)(aux + pwords);
-    MPG_TRY(hipMemsetAsync(status, 0, sizeof(int32_t), s));
+    int32_t* status = info_dev ? info_dev : (int32_t*)(aux + pwords);
+    MPG_TRY(launch_fill_i32(status, 1, 0, s));
     Bases bs{};
     bs.p[BASE_A] = A;
     const MatRef a{BASE_A, 0, 0, lda, psa};
@@ -46,15 +48,16 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
         const int64_t kb = (panel < n - j0) ? panel : n - j0;
         const int64_t je = j0 + kb;
         for (int64_t c = j0; c < je; c++) {
-            MPG_TRY(launch_lu_pivot(L, bs, a, n, c, piv, status, s));
-            MPG_TRY(launch_lu_swap(L, bs, a, c, piv, j0, je, s));
-            MPG_TRY(launch_lu_scale(L, bs, a, n, c, s));
-            MPG_TRY(launch_lu_rank1(L, bs, a, c, c + 1, n, c + 1, je, s));
+            // pivot search and the swap inside the panel; then multipliers and
+            // the panel's rank-one update (a zero pivot leaves a zero column, whose
+            // quotients and updates are exact no-ops)
+            MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, s));
+            MPG_TRY(launch_lu_eliminate(L, bs, a, n, c, je, s));
         }
         MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, n, s));
         MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, je, n, n, s));
         if (je >= n) break;
-        for (int64_t t = j0; t < je - 1; t++) MPG_TRY(launch_lu_rank1(L, bs, a, t, t + 1, je, je, n, s));
+        MPG_TRY(launch_lu_u12(L, bs, a, j0, kb, je, n, s));
         const int64_t m2 = n - je;
         uint32_t* P = aux;
         const uint32_t* L21 = A + je * lda + j0;
@@ -65,8 +68,24 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
             return rc;
         if ((rc = ew_internal(OP_SUB, m2, m2, L, A22, lda, psa, P, m2, m2 * m2, A22, lda, psa, s))) return rc;
     }
-    MPG_TRY(hipMemcpyAsync(info_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    MPG_TRY(hipStreamSynchronize(s));
+    if (info_host) {
+        MPG_TRY(hipMemcpyAsync(info_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MPG_TRY(hipStreamSynchronize(s));
+    }
+    return MP_OK;
+}
+
+int lu_check(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int panel, int algo,
+             int cutoff, int policy, int* L)
+{
+    int rc;
+    if ((rc = check_prec(prec, L))) return rc;
+    if ((rc = check_mat("A", A, n, n, lda, psa))) return rc;
+    if (panel < 1) return set_err(MP_E_ARG, "panel must be >= 1");
+    if (algo < ALGO_SIMPLE || algo > ALGO_WINOGRAD) return set_err(MP_E_ARG, "unknown algorithm");
+    if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
+    if (policy < POLICY_PEEL || policy > POLICY_MIXED) return set_err(MP_E_ARG, "unknown odd-size policy");
+    if (n > 0 && !piv) return set_err(MP_E_ARG, "piv is NULL");
     return MP_OK;
 }
 
@@ -78,18 +97,24 @@ int mp_lu_ex(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int32_t
              int algo, int cutoff, int policy)
 {
     int L, rc;
-    if ((rc = check_prec(prec, &L))) return rc;
     if (!info) return set_err(MP_E_ARG, "info is NULL");
     *info = 0;
-    if ((rc = check_mat("A", A, n, n, lda, psa))) return rc;
-    if (panel < 1) return set_err(MP_E_ARG, "panel must be >= 1");
-    if (algo < ALGO_SIMPLE || algo > ALGO_WINOGRAD) return set_err(MP_E_ARG, "unknown algorithm");
-    if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
-    if (policy < POLICY_PEEL || policy > POLICY_MIXED) return set_err(MP_E_ARG, "unknown odd-size policy");
+    if ((rc = lu_check(n, prec, A, lda, psa, piv, panel, algo, cutoff, policy, &L))) return rc;
     if (n == 0) return MP_OK;
-    if (!piv) return set_err(MP_E_ARG, "piv is NULL");
     if ((rc = device_check())) return rc;
-    if ((rc = lu_run(n, L, A, lda, psa, piv, info, panel, algo, cutoff, policy, g_stream))) return rc;
+    if ((rc = lu_run(n, L, A, lda, psa, piv, info, nullptr, panel, algo, cutoff, policy, g_stream))) return rc;
+    return device_check();
+}
+
+int mp_lu_async(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info_dev,
+                int panel, int algo, int cutoff, int policy)
+{
+    int L, rc;
+    if (!info_dev) return set_err(MP_E_ARG, "info_dev is NULL");
+    if ((rc = lu_check(n, prec, A, lda, psa, piv, panel, algo, cutoff, policy, &L))) return rc;
+    if (n == 0) return launch_fill_i32(info_dev, 1, 0, g_stream) == hipSuccess ? MP_OK : MP_E_DEVICE;
+    if ((rc = device_check())) return rc;
+    if ((rc = lu_run(n, L, A, lda, psa, piv, nullptr, info_dev, panel, algo, cutoff, policy, g_stream))) return rc;
     return device_check();
 }
 

@@ -28,7 +28,7 @@
 
 namespace mpg {
 
-enum Algo { ALGO_SIMPLE = 0, ALGO_BLOCK = 1, ALGO_STRASSEN = 2, ALGO_WINOGRAD = 3 };
+enum Algo { ALGO_SIMPLE = 0, ALGO_BLOCK = 1, ALGO_STRASSEN = 2, ALGO_WINOGRAD = 3, ALGO_AUTO = 4 };
 enum Policy { POLICY_PEEL = 0, POLICY_PAD = 1, POLICY_MIXED = 2 };
 
 struct Step {

@@ -48,16 +48,20 @@ int slice_internal(int64_t m, int64_t l, int64_t n, int L, int extra, const uint
                    int32_t* window_out, hipStream_t s)
 {
     const int p = 32 * L;
-    const int64_t mpad = round_up(m, SLICE_TILE), npad = round_up(n, SLICE_TILE);
+    const int64_t mpad = round_up(m, SLICE_TILE_M), npad = round_up(n, SLICE_TILE_N);
     const int64_t kpad = round_up(std::max<int64_t>(l, 1), SLICE_KSTEP);
     // scratch: exponent tables (4 arrays), then the digit planes, then G
     int rc = MP_OK;
-    const size_t exp_words = (size_t)(2 * m + 2 * n + 64);
+    const int64_t nchunks = (std::max<int64_t>(l, 1) + 63) / 64;
+    const size_t exp_words = (size_t)(2 * m + 2 * n + 2 * nchunks * n + 64);
     uint32_t* base = workspace(exp_words, s, WS_SLICE_EXP, &rc);
     if (rc) return rc;
-    int32_t *ea = (int32_t*)base, *ea_lo = ea + m, *fb = ea_lo + m, *fb_lo = fb + n;
-    SL_TRY(launch_slice_scan(L, A, lda, psa, m, l, 0, ea, ea_lo, s));
-    SL_TRY(launch_slice_scan(L, B, ldb, psb, n, l, 1, fb, fb_lo, s));
+    int32_t *ea = (int32_t*)base, *ea_lo = ea + m, *fb = ea_lo + m, *fb_lo = fb + n, *tmp = fb_lo + n;
+    {
+        ProfScope ps(s, 3, 2, L, (double)(m + n) * l, 0);
+        SL_TRY(launch_slice_scan(L, A, lda, psa, m, l, 0, ea, ea_lo, tmp, s));
+        SL_TRY(launch_slice_scan(L, B, ldb, psb, n, l, 1, fb, fb_lo, tmp, s));
+    }
     std::vector<int32_t> h(2 * (size_t)m + 2 * (size_t)n);
     SL_TRY(hipMemcpyAsync(h.data(), base, h.size() * 4, hipMemcpyDeviceToHost, s));
     SL_TRY(hipStreamSynchronize(s));
@@ -82,15 +86,34 @@ int slice_internal(int64_t m, int64_t l, int64_t n, int L, int extra, const uint
             slots.push_back(Slot{u, s0, (int)std::min<int64_t>(hi, s0 + pairs_per_slot)});
         slot_begin.push_back((int32_t)slots.size());
     }
-    std::vector<SliceTask> tasks;
-    const int ti_n = (int)(mpad / SLICE_TILE), tj_n = (int)(npad / SLICE_TILE);
+    std::vector<SliceTask> order;
+    const int ti_n = (int)(mpad / SLICE_TILE_M), tj_n = (int)(npad / SLICE_TILE_N);
     for (size_t q = 0; q < slots.size(); q++)
         for (int ti = 0; ti < ti_n; ti++)
             for (int tj = 0; tj < tj_n; tj++)
-                tasks.push_back(SliceTask{slots[q].u, slots[q].s0, slots[q].s1, (int32_t)q, ti, tj});
-    // longest first: the grid drains evenly
-    std::stable_sort(tasks.begin(), tasks.end(),
+                order.push_back(SliceTask{slots[q].u, slots[q].s0, slots[q].s1, (int32_t)q, ti, tj});
+    // longest first, so the grid drains evenly; neighbours in this order share
+    // digit tiles of A or B
+    std::stable_sort(order.begin(), order.end(),
                      [](const SliceTask& a, const SliceTask& b) { return (a.s1 - a.s0) > (b.s1 - b.s0); });
+    // workgroups are dealt to the 8 XCDs round robin (block b on XCD b mod 8):
+    // give each XCD runs of RUN consecutive tasks, runs dealt round robin, so an
+    // XCD's L2 sees neighbouring tiles and the XCDs stay balanced
+    const size_t NX = 8, RUN = 16, nt = order.size();
+    std::vector<SliceTask> tasks(nt);
+    // block indices of XCD x are x, x + 8, x + 16, ... while every XCD has
+    // work; the tail (unequal counts) is filled in order
+    {
+        // build the block order: round r of the dispatch takes the next task of
+        // every XCD that still has one
+        std::vector<std::vector<size_t>> lists(NX);
+        for (size_t r = 0; r * RUN < nt; r++)
+            for (size_t q = r * RUN; q < std::min(nt, (r + 1) * RUN); q++) lists[r % NX].push_back(q);
+        size_t b = 0;
+        for (size_t round = 0; b < nt; round++)
+            for (size_t x = 0; x < NX; x++)
+                if (round < lists[x].size()) tasks[b++] = order[lists[x][round]];
+    }
     const int64_t a_plane = mpad * kpad, b_plane = npad * kpad, g_plane = mpad * npad;
     const size_t bytes_a = (size_t)SA * a_plane, bytes_b = (size_t)SB * b_plane;
     const size_t bytes_g = (size_t)slots.size() * g_plane * 4;

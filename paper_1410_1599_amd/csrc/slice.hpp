@@ -15,17 +15,18 @@ constexpr int SLICE_NWZ4 = 15, SLICE_NWZ8 = 23, SLICE_NWZ16 = 39;
 // |digit| <= 128, so a product is at most 2^14 and an INT32 sum of K of them
 // is exact while K * 2^14 < 2^31
 constexpr int64_t SLICE_KMAX = 131008;
-constexpr int SLICE_TILE = 128, SLICE_KSTEP = 64;
+constexpr int SLICE_TILE_M = 256, SLICE_TILE_N = 128, SLICE_KSTEP = 64;
 
 struct SliceTask {
     int32_t u;       // diagonal: pairs (s, u - s)
     int32_t s0, s1;  // pairs s0 <= s < s1
     int32_t slot;    // output plane of G
-    int32_t ti, tj;  // 128 x 128 output tile
+    int32_t ti, tj;  // SLICE_TILE_M x SLICE_TILE_N output tile
 };
 
+// tmp: 2 * ceil(inner / 64) * outer int32 of scratch (column scan only)
 hipError_t launch_slice_scan(int L, const uint32_t* X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
-                             int by_cols, int32_t* emax, int32_t* emin, hipStream_t s);
+                             int by_cols, int32_t* emax, int32_t* emin, int32_t* tmp, hipStream_t s);
 hipError_t launch_slice_digits(int L, const uint32_t* X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
                                int by_cols, const int32_t* emax, int32_t W, int32_t S, int8_t* D, int64_t dps,
                                int64_t outer_pad, int64_t kpad, hipStream_t s);

@@ -23,23 +23,81 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ exponent scan
 
-// per row (A) or per column (B): largest and smallest exponent of the nonzero
-// entries; a zero row reports max = min = INT32_MIN
+// Largest and smallest exponent of the nonzero entries of every row (A) or
+// column (B); a zero row or column reports max = min = INT32_MIN.
+//
+// Rows: one workgroup per row, threads across the row (coalesced), LDS tree.
+// Columns: a workgroup takes 256 consecutive columns and a chunk of SCAN_ROWS
+// rows (coalesced across threads) and writes a partial result per chunk; a
+// second small pass folds the chunks.
+constexpr int SCAN_ROWS = 64;
+
+__device__ __forceinline__ void fold(int32_t& hi, int32_t& lo, int32_t h2, int32_t l2)
+{
+    hi = h2 > hi ? h2 : hi;
+    lo = l2 < lo ? l2 : lo;
+}
+
 template <int L>
 __global__ void __launch_bounds__(256)
-k_slice_scan(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer, int64_t inner, int by_cols,
-             int32_t* __restrict__ emax, int32_t* __restrict__ emin)
+k_slice_scan_rows(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t inner, int32_t* __restrict__ emax,
+                  int32_t* __restrict__ emin)
+{
+    __shared__ int32_t sh[256], sl[256];
+    const int64_t o = blockIdx.x;
+    int32_t hi = INT32_MIN, lo = INT32_MAX;
+    for (int64_t q = threadIdx.x; q < inner; q += 256) {
+        const int64_t idx = o * ld + q;
+        if (X[(L - 1) * ps + idx] == 0) continue;
+        const int32_t e = (int32_t)X[L * ps + idx];
+        fold(hi, lo, e, e);
+    }
+    sh[threadIdx.x] = hi;
+    sl[threadIdx.x] = lo;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            int32_t h = sh[threadIdx.x], l = sl[threadIdx.x];
+            fold(h, l, sh[threadIdx.x + s], sl[threadIdx.x + s]);
+            sh[threadIdx.x] = h;
+            sl[threadIdx.x] = l;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        emax[o] = sh[0];
+        emin[o] = sh[0] == INT32_MIN ? INT32_MIN : sl[0];
+    }
+}
+
+template <int L>
+__global__ void __launch_bounds__(256)
+k_slice_scan_cols(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
+                  int32_t* __restrict__ phi, int32_t* __restrict__ plo)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (o >= outer) return;
+    int32_t hi = INT32_MIN, lo = INT32_MAX;
+    const int64_t q1 = (chunk + 1) * SCAN_ROWS < inner ? (chunk + 1) * SCAN_ROWS : inner;
+    for (int64_t q = chunk * SCAN_ROWS; q < q1; q++) {
+        const int64_t idx = q * ld + o;
+        if (X[(L - 1) * ps + idx] == 0) continue;
+        const int32_t e = (int32_t)X[L * ps + idx];
+        fold(hi, lo, e, e);
+    }
+    phi[chunk * outer + o] = hi;
+    plo[chunk * outer + o] = lo;
+}
+
+__global__ void __launch_bounds__(256)
+k_slice_scan_fold(const int32_t* __restrict__ phi, const int32_t* __restrict__ plo, int64_t outer, int64_t nchunks,
+                  int32_t* __restrict__ emax, int32_t* __restrict__ emin)
 {
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (o >= outer) return;
     int32_t hi = INT32_MIN, lo = INT32_MAX;
-    for (int64_t q = 0; q < inner; q++) {
-        const int64_t idx = by_cols ? q * ld + o : o * ld + q;
-        if (X[(L - 1) * ps + idx] == 0) continue;
-        const int32_t e = (int32_t)X[L * ps + idx];
-        hi = e > hi ? e : hi;
-        lo = e < lo ? e : lo;
-    }
+    for (int64_t c = 0; c < nchunks; c++) fold(hi, lo, phi[c * outer + o], plo[c * outer + o]);
     emax[o] = hi;
     emin[o] = hi == INT32_MIN ? INT32_MIN : lo;
 }
@@ -141,16 +199,22 @@ k_slice_digits(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t o
 
 // ------------------------------------------------------------------ INT8 products
 
-constexpr int TM = 128, TN = 128, TKK = 64, LDSW = TKK + 16;
+constexpr int TM = SLICE_TILE_M, TN = SLICE_TILE_N, TKK = SLICE_KSTEP, LDSW = TKK + 16;
+constexpr int GT = 512;                            // 8 waves: 4 (rows) x 2 (columns) of 64 x 64
+constexpr int CHA = TM * TKK / 16 / GT;            // 16-byte chunks of A per thread and step
+constexpr int CHB = TN * TKK / 16 / GT;
 
-// one workgroup: a 128 x 128 tile of G_slot = sum_{s = s0}^{s1 - 1} A8_s B8_{u-s}^T
-__global__ void __launch_bounds__(256)
+// One workgroup: a 256 x 128 tile of G_slot = sum_{s = s0}^{s1 - 1} A8_s B8_{u-s}^T.
+// The inner loop walks (pair, 64-wide k step); the next step's operands are
+// loaded into registers while the matrix cores work on the current one, then
+// written to the other LDS buffer (one barrier per step).
+__global__ void __launch_bounds__(GT)
 k_slice_gemm(const SliceTask* __restrict__ tasks, const int8_t* __restrict__ A8, const int8_t* __restrict__ B8,
              int32_t* __restrict__ G, int64_t a_plane, int64_t b_plane, int64_t g_plane, int32_t kpad,
              int32_t npad)
 {
-    __shared__ __attribute__((aligned(16))) int8_t sA[TM][LDSW];
-    __shared__ __attribute__((aligned(16))) int8_t sB[TN][LDSW];
+    __shared__ __attribute__((aligned(16))) int8_t sA[2][TM][LDSW];
+    __shared__ __attribute__((aligned(16))) int8_t sB[2][TN][LDSW];
     const SliceTask T = tasks[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wy = wave >> 1, wx = wave & 1;
@@ -160,29 +224,58 @@ k_slice_gemm(const SliceTask* __restrict__ tasks, const int8_t* __restrict__ A8,
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = (v4i){0, 0, 0, 0};
     const int64_t i0 = (int64_t)T.ti * TM, j0 = (int64_t)T.tj * TN;
-    for (int s = T.s0; s < T.s1; s++) {
-        const int8_t* Ap = A8 + (int64_t)s * a_plane + i0 * kpad;
-        const int8_t* Bp = B8 + (int64_t)(T.u - s) * b_plane + j0 * kpad;
-        for (int k0 = 0; k0 < kpad; k0 += TKK) {
-            __syncthreads();
-            for (int c = tid; c < TM * TKK / 16; c += 256) {
-                const int r = c >> 2, q = c & 3;
-                *(v4i*)&sA[r][q * 16] = *(const v4i*)(Ap + (int64_t)r * kpad + k0 + q * 16);
-                *(v4i*)&sB[r][q * 16] = *(const v4i*)(Bp + (int64_t)r * kpad + k0 + q * 16);
-            }
-            __syncthreads();
-            v4i af[4], bf[4];
+    const int ksteps = kpad / TKK;
+    const int nsteps = (T.s1 - T.s0) * ksteps;
+    v4i ra[CHA], rb[CHB];
+    auto fetch = [&](int step) {
+        const int s = T.s0 + step / ksteps;
+        const int k0 = (step % ksteps) * TKK;
+        const int8_t* Ap = A8 + (int64_t)s * a_plane + i0 * kpad + k0;
+        const int8_t* Bp = B8 + (int64_t)(T.u - s) * b_plane + j0 * kpad + k0;
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
-                af[t] = *(const v4i*)&sA[wy * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
-                bf[t] = *(const v4i*)&sB[wx * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
-            }
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int b = 0; b < 4; b++)
-                    acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+        for (int c = 0; c < CHA; c++) {
+            const int q = tid + c * GT;
+            ra[c] = *(const v4i*)(Ap + (int64_t)(q >> 2) * kpad + (q & 3) * 16);
         }
+#pragma unroll
+        for (int c = 0; c < CHB; c++) {
+            const int q = tid + c * GT;
+            rb[c] = *(const v4i*)(Bp + (int64_t)(q >> 2) * kpad + (q & 3) * 16);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < CHA; c++) {
+            const int q = tid + c * GT;
+            *(v4i*)&sA[buf][q >> 2][(q & 3) * 16] = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CHB; c++) {
+            const int q = tid + c * GT;
+            *(v4i*)&sB[buf][q >> 2][(q & 3) * 16] = rb[c];
+        }
+    };
+    if (nsteps > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    for (int step = 0; step < nsteps; step++) {
+        const int buf = step & 1;
+        if (step + 1 < nsteps) fetch(step + 1);
+        v4i af[4], bf[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            af[t] = *(const v4i*)&sA[buf][wy * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
+            bf[t] = *(const v4i*)&sB[buf][wx * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+        if (step + 1 < nsteps) stash(buf ^ 1);
+        __syncthreads();
     }
     int32_t* Gp = G + (int64_t)T.slot * g_plane;
 #pragma unroll
@@ -296,16 +389,31 @@ k_slice_combine(const int32_t* __restrict__ G, int64_t g_plane, int32_t npad, co
 }  // namespace
 
 hipError_t launch_slice_scan(int L, const uint32_t* X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
-                             int by_cols, int32_t* emax, int32_t* emin, hipStream_t s)
+                             int by_cols, int32_t* emax, int32_t* emin, int32_t* tmp, hipStream_t s)
 {
     if (outer <= 0) return hipSuccess;
-    const dim3 g((unsigned)((outer + 255) / 256));
+    if (!by_cols) {
+        const dim3 g((unsigned)outer);
+        switch (L) {
+        case 4: hipLaunchKernelGGL((k_slice_scan_rows<4>), g, dim3(256), 0, s, X, ld, ps, inner, emax, emin); break;
+        case 8: hipLaunchKernelGGL((k_slice_scan_rows<8>), g, dim3(256), 0, s, X, ld, ps, inner, emax, emin); break;
+        case 16: hipLaunchKernelGGL((k_slice_scan_rows<16>), g, dim3(256), 0, s, X, ld, ps, inner, emax, emin); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    const int64_t nchunks = inner > 0 ? (inner + SCAN_ROWS - 1) / SCAN_ROWS : 1;
+    int32_t* phi = tmp;
+    int32_t* plo = tmp + nchunks * outer;
+    const dim3 g((unsigned)((outer + 255) / 256), (unsigned)nchunks);
     switch (L) {
-    case 4: hipLaunchKernelGGL((k_slice_scan<4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, emin); break;
-    case 8: hipLaunchKernelGGL((k_slice_scan<8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, emin); break;
-    case 16: hipLaunchKernelGGL((k_slice_scan<16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, emin); break;
+    case 4: hipLaunchKernelGGL((k_slice_scan_cols<4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, phi, plo); break;
+    case 8: hipLaunchKernelGGL((k_slice_scan_cols<8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, phi, plo); break;
+    case 16: hipLaunchKernelGGL((k_slice_scan_cols<16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, phi, plo); break;
     default: return hipErrorInvalidValue;
     }
+    hipLaunchKernelGGL(k_slice_scan_fold, dim3((unsigned)((outer + 255) / 256)), dim3(256), 0, s, phi, plo, outer,
+                       nchunks, emax, emin);
     return hipGetLastError();
 }
 
@@ -330,7 +438,7 @@ hipError_t launch_slice_gemm(const SliceTask* tasks, int64_t ntasks, const int8_
                              hipStream_t s)
 {
     if (ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_slice_gemm, dim3((unsigned)ntasks), dim3(256), 0, s, tasks, A8, B8, G, a_plane, b_plane,
+    hipLaunchKernelGGL(k_slice_gemm, dim3((unsigned)ntasks), dim3(GT), 0, s, tasks, A8, B8, G, a_plane, b_plane,
                        g_plane, kpad, npad);
     return hipGetLastError();
 }

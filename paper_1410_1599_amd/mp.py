@@ -16,8 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmpgemm.so")
 
-SIMPLE, BLOCK, STRASSEN, WINOGRAD = 0, 1, 2, 3
-ALGOS = {"simple": SIMPLE, "block": BLOCK, "strassen": STRASSEN, "winograd": WINOGRAD}
+SIMPLE, BLOCK, STRASSEN, WINOGRAD, AUTO = 0, 1, 2, 3, 4
+ALGOS = {"simple": SIMPLE, "block": BLOCK, "strassen": STRASSEN, "winograd": WINOGRAD, "auto": AUTO}
 PEEL, PAD, MIXED = 0, 1, 2
 POLICIES = {"peel": PEEL, "pad": PAD, "mixed": MIXED}
 LEAF_SIMPLE, LEAF_BLOCK = 0, 1
@@ -56,6 +56,12 @@ def _load():
         "mp_release_workspace": ([], i32),
         "mp_profile": ([i32], i32),
         "mp_gemm_slice": ([i64, i64, i64, i32, i32] + mat * 3 + [i32p], i32),
+        "mp_set_graph_mode": ([i32], i32),
+        "mp_tune": ([i64, i64, i64, i32, i32, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float)], i32),
+        "mp_auto_choice": ([i64, i64, i64, i32, i32p, i32p, i32p], i32),
+        "mp_tune_save": ([ctypes.c_char_p], i32),
+        "mp_tune_load": ([ctypes.c_char_p], i32),
+        "mp_lu_async": ([i64, i32, vp, i64, i64, vp, vp, i32, i32, i32, i32], i32),
         "mp_profile_read": ([i32, i32p, i32p, i32p, dp, i64p, ctypes.POINTER(ctypes.c_float)], i32),
     }
     for name, (args, res) in sig.items():
@@ -212,3 +218,39 @@ def mp_profile_read(max_records=4096):
     units, nt, ms = (ctypes.c_double * n)(), (ctypes.c_int64 * n)(), (ctypes.c_float * n)()
     got = lib.mp_profile_read(n, kind, op, L, units, nt, ms)
     return [dict(kind=kind[i], op=op[i], L=L[i], units=units[i], ntiles=nt[i], ms=ms[i]) for i in range(min(got, n))]
+
+
+def mp_set_graph_mode(enable):
+    return _check(lib.mp_set_graph_mode(1 if enable else 0))
+
+
+def mp_tune(m, l, n, prec, reps=2):
+    mp_set_stream()
+    a, c, lf = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    t = ctypes.c_float(0)
+    _check(lib.mp_tune(m, l, n, prec, reps, ctypes.byref(a), ctypes.byref(c), ctypes.byref(lf), ctypes.byref(t)))
+    return {"algo": a.value, "cutoff": c.value, "leaf": lf.value, "ms": t.value}
+
+
+def mp_auto_choice(m, l, n, prec):
+    a, c, lf = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib.mp_auto_choice(m, l, n, prec, ctypes.byref(a), ctypes.byref(c), ctypes.byref(lf)))
+    return {"algo": a.value, "cutoff": c.value, "leaf": lf.value}
+
+
+def mp_tune_save(path):
+    return _check(lib.mp_tune_save(path.encode()))
+
+
+def mp_tune_load(path):
+    got = lib.mp_tune_load(path.encode())
+    if got < 0:
+        raise MPError(got, last_error())
+    return got
+
+
+def mp_lu_async(n, prec, A, piv, info_dev, panel=64, algo=WINOGRAD, cutoff=32, policy=PEEL):
+    mp_set_stream()
+    pa, lda, psa = _mat(A)
+    return _check(lib.mp_lu_async(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()),
+                                  ctypes.c_void_p(info_dev.data_ptr()), int(panel), int(algo), int(cutoff), int(policy)))
