@@ -126,6 +126,22 @@ int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, 
                uint32_t *C, int64_t ldc, int64_t psc);
 
 /*
+ * A batch of `count` products C_r := A_r B_r of one precision with one
+ * algorithm and cutoff, shapes free (host arrays of count entries; the
+ * matrices are device buffers in plane layout).  All products are planned
+ * together: every recursion level's passes of all items share one grouped
+ * launch, and every leaf product of every item shares one launch (the
+ * paper's seven sub-products per level and many uneven products issued
+ * together).  Each C_r is bit-identical to mp_gemm of that item alone.
+ * Results must not overlap one another or any operand.  Items with m or n
+ * zero are skipped.  Odd sizes and leaf kernel follow mp_set_policy.
+ */
+int mp_gemm_batched(int count, const int64_t *m, const int64_t *l, const int64_t *n, int prec, int algo, int cutoff,
+                    const uint32_t *const *A, const int64_t *lda, const int64_t *psa,
+                    const uint32_t *const *B, const int64_t *ldb, const int64_t *psb,
+                    uint32_t *const *C, const int64_t *ldc, const int64_t *psc);
+
+/*
  * Elementwise C := A op B on m x n matrices, one rounding per element: the
  * matrix additions and subtractions of Strassen's and Winograd's levels
  * (Section 2), and products and true quotients for completeness.  C may alias
@@ -219,6 +235,14 @@ int mp_lu_solve(int64_t n, int prec, const uint32_t *LU, int64_t lda, int64_t ps
  */
 int mp_profile(int enable);
 int mp_profile_read(int max, int *kind, int *op, int *L, double *units, int64_t *ntiles, float *ms);
+
+/*
+ * Fill the rows x cols matrix X with seeded p-bit values uniform on (-1, 1):
+ * x = +-W 2^-p, W a p-bit integer hashed from (seed, element index, limb),
+ * normalised (so device-resident test and request operands need no host
+ * copy).  Asynchronous.
+ */
+int mp_fill_uniform(int64_t rows, int64_t cols, int prec, uint32_t *X, int64_t ld, int64_t ps, uint64_t seed);
 
 /*
  * Graph mode (process-wide, default off): each mp_gemm / mp_add-style call

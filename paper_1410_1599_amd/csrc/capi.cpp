@@ -545,6 +545,84 @@ int mp_profile_read(int max, int* kind, int* op, int* L, double* units, int64_t*
     return n;
 }
 
+int mp_gemm_batched(int count, const int64_t* m, const int64_t* l, const int64_t* n, int prec, int algo, int cutoff,
+                    const uint32_t* const* A, const int64_t* lda, const int64_t* psa, const uint32_t* const* B,
+                    const int64_t* ldb, const int64_t* psb, uint32_t* const* C, const int64_t* ldc, const int64_t* psc)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if (count < 0) return set_err(MP_E_ARG, "negative count");
+    if (count == 0) return MP_OK;
+    if (!m || !l || !n || !A || !lda || !psa || !B || !ldb || !psb || !C || !ldc || !psc)
+        return set_err(MP_E_ARG, "a batch array is NULL");
+    if (algo < ALGO_SIMPLE || algo > ALGO_WINOGRAD) return set_err(MP_E_ARG, "unknown algorithm");
+    if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
+    std::vector<BatchItem> items;
+    std::vector<uint32_t*> table;
+    for (int r = 0; r < count; r++) {
+        if (m[r] < 0 || l[r] < 0 || n[r] < 0) return set_err(MP_E_ARG, "negative dimension");
+        if ((rc = check_mat("A", A[r], m[r], l[r], lda[r], psa[r])) || (rc = check_mat("B", B[r], l[r], n[r], ldb[r], psb[r])) ||
+            (rc = check_mat("C", C[r], m[r], n[r], ldc[r], psc[r])))
+            return rc;
+        if (m[r] == 0 || n[r] == 0) continue;
+        if (l[r] > 0 && (overlaps(C[r], psc[r], A[r], psa[r], L) || overlaps(C[r], psc[r], B[r], psb[r], L)))
+            return set_err(MP_E_ALIAS, "C overlaps A or B");
+        for (size_t q = 0; q < table.size(); q += 3)
+            if (overlaps(C[r], psc[r], table[q + 2], items[q / 3].psc, L))
+                return set_err(MP_E_ALIAS, "two results of the batch overlap");
+        items.push_back(BatchItem{m[r], l[r], n[r], lda[r], psa[r], ldb[r], psb[r], ldc[r], psc[r]});
+        table.push_back(const_cast<uint32_t*>(A[r]));
+        table.push_back(const_cast<uint32_t*>(B[r]));
+        table.push_back(C[r]);
+    }
+    if (items.empty()) return MP_OK;
+    if ((rc = device_check())) return rc;
+    hipStream_t s = g_stream;
+    Plan P;
+    PlanKey key{0, 0, 0, L, algo, (algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) ? cutoff : 0, g_policy,
+                algo == ALGO_BLOCK ? 1 : g_leaf, 0, 0, 0, 0, 0, 0};
+    build_plan_batched(P, key, items);
+    const char* why = nullptr;
+    if (!validate_plan(P, &why)) return set_err(MP_E_ARG, why);
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t bg = al(P.gemm.size() * sizeof(GemmTask)), bn = al(P.node.size() * sizeof(NodeTask));
+    const size_t bt = al(P.tiles.size() * 4), bb = al(table.size() * sizeof(uint32_t*));
+    uint8_t* buf = (uint8_t*)workspace((bg + bn + bt + bb) / 4 + 64, s, WS_BATCH, &rc);
+    if (rc) return rc;
+    P.d_gemm = (GemmTask*)buf;
+    P.d_node = (NodeTask*)(buf + bg);
+    P.d_tiles = (int32_t*)(buf + bg + bn);
+    uint32_t** d_table = (uint32_t**)(buf + bg + bn + bt);
+    // pageable sources: each copy has read its source when the call returns
+    if ((!P.gemm.empty() && hipMemcpyAsync(P.d_gemm, P.gemm.data(), P.gemm.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s)) ||
+        (!P.node.empty() && hipMemcpyAsync(P.d_node, P.node.data(), P.node.size() * sizeof(NodeTask), hipMemcpyHostToDevice, s)) ||
+        (!P.tiles.empty() && hipMemcpyAsync(P.d_tiles, P.tiles.data(), P.tiles.size() * 4, hipMemcpyHostToDevice, s)) ||
+        hipMemcpyAsync(d_table, table.data(), table.size() * sizeof(uint32_t*), hipMemcpyHostToDevice, s))
+        return set_err(MP_E_DEVICE, "batch upload failed");
+    Bases bs{};
+    bs.ext = d_table;
+    bs.p[BASE_WS] = workspace((size_t)P.ws_words, s, WS_PLAN, &rc);
+    if (rc) return rc;
+    rc = launch_steps(P, bs, s);
+    P.d_gemm = nullptr;                        // the buffer belongs to the workspace
+    P.d_node = nullptr;
+    P.d_tiles = nullptr;
+    if (rc) return rc;
+    return device_check();
+}
+
+int mp_fill_uniform(int64_t rows, int64_t cols, int prec, uint32_t* X, int64_t ld, int64_t ps, uint64_t seed)
+{
+    int L, rc;
+    if ((rc = check_prec(prec, &L))) return rc;
+    if ((rc = check_mat("X", X, rows, cols, ld, ps))) return rc;
+    if (rows == 0 || cols == 0) return MP_OK;
+    if ((rc = device_check())) return rc;
+    if (launch_fill_uniform(L, X, ld, ps, rows, cols, seed, g_stream) != hipSuccess)
+        return set_err(MP_E_DEVICE, "fill launch failed");
+    return device_check();
+}
+
 int mp_set_graph_mode(int enable)
 {
     g_graph_mode = enable ? 1 : 0;
@@ -579,8 +657,8 @@ int mp_tune(int64_t m, int64_t l, int64_t n, int prec, int reps, int* algo, int*
         return set_err(MP_E_NOMEM, "tuner scratch allocation failed");
     }
     uint32_t *A = buf, *B = buf + wa, *C = buf + wa + wb;
-    if (launch_fill_uniform(L, A, m * l, m * l, 12345u, s) != hipSuccess ||
-        launch_fill_uniform(L, B, l * n, l * n, 67890u, s) != hipSuccess) {
+    if (launch_fill_uniform(L, A, l, m * l, m, l, 12345u, s) != hipSuccess ||
+        launch_fill_uniform(L, B, n, l * n, l, n, 67890u, s) != hipSuccess) {
         (void)hipFree(buf);
         return set_err(MP_E_DEVICE, "tuner fill failed");
     }

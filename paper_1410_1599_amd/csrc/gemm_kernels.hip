@@ -21,7 +21,7 @@ namespace mpg {
 template <int L>
 __device__ __forceinline__ const uint32_t* ref_ptr(const Bases& b, const MatRef& r)
 {
-    return b.p[r.base] + r.off;
+    return base_ptr(b, r.base) + r.off;
 }
 
 // ------------------------------------------------------------------ Simple
@@ -42,7 +42,7 @@ k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ ti
         if (i >= T.m || j >= T.n) continue;
         const uint32_t* A = ref_ptr<L>(bs, T.A) + i * T.A.ld;
         const uint32_t* B = ref_ptr<L>(bs, T.B) + j;
-        uint32_t* C = bs.p[T.C.base] + T.C.off + i * T.C.ld + j;
+        uint32_t* C = base_ptr(bs, T.C.base) + T.C.off + i * T.C.ld + j;
         MP<L> c = T.accum ? load<L>(C, T.C.ps, 0) : mp_zero<L>();
         for (int k = 0; k < T.l; k++) {
             const MP<L> a = load<L>(A, T.A.ps, k);
@@ -75,7 +75,7 @@ k_gemm_block(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ til
         const bool live = (i < T.m) && (j < T.n);
         const uint32_t* A = ref_ptr<L>(bs, T.A);
         const uint32_t* B = ref_ptr<L>(bs, T.B);
-        uint32_t* C = bs.p[T.C.base] + T.C.off;
+        uint32_t* C = base_ptr(bs, T.C.base) + T.C.off;
         MP<L> c = (T.accum && live) ? load<L>(C + i * T.C.ld + j, T.C.ps, 0) : mp_zero<L>();
         for (int k0 = 0; k0 < T.l; k0 += TK) {
             __syncthreads();
@@ -124,13 +124,13 @@ k_gemm_block(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ til
 template <int L>
 __device__ __forceinline__ MP<L> ld(const Bases& bs, const MatRef& r, int64_t i, int64_t j)
 {
-    return load<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j);
+    return load<L>(base_ptr(bs, r.base) + r.off, r.ps, i * r.ld + j);
 }
 
 template <int L>
 __device__ __forceinline__ void st(const Bases& bs, const MatRef& r, int64_t i, int64_t j, const MP<L>& v)
 {
-    store<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j, v);
+    store<L>(base_ptr(bs, r.base) + r.off, r.ps, i * r.ld + j, v);
 }
 
 template <int L, int OP>
@@ -234,17 +234,44 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     return x;
 }
 
+// Seeded values uniform on (-1, 1): W = L hashed words read as a p-bit
+// integer, x = +-W 2^-p (sign from the hash), normalised; W = 0 is zero.
 template <int L>
-__global__ void __launch_bounds__(256) k_fill_uniform(uint32_t* X, int64_t ps, int64_t count, uint32_t seed)
+__global__ void __launch_bounds__(256)
+k_fill_uniform(uint32_t* X, int64_t ld, int64_t ps, int64_t rows, int64_t cols, uint64_t seed)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= count) return;
-    const uint32_t h = mix32(seed ^ mix32((uint32_t)i ^ mix32((uint32_t)(i >> 32))));
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int64_t i = e / cols, j = e % cols;
+    const uint32_t h = mix32((uint32_t)seed ^ mix32((uint32_t)(seed >> 32) ^ mix32((uint32_t)e ^ mix32((uint32_t)(e >> 32)))));
+    uint32_t w[L];
 #pragma unroll
-    for (int k = 0; k < L; k++) X[k * ps + i] = mix32(h + 0x9e3779b9u * (k + 1));
-    X[(L - 1) * ps + i] |= 0x80000000u;
-    X[L * ps + i] = (uint32_t)(-(int32_t)(h & 3));
-    X[(L + 1) * ps + i] = (h >> 2) & 1;
+    for (int k = 0; k < L; k++) w[k] = mix32(h + 0x9e3779b9u * (uint32_t)(k + 1));
+    int32_t top = -1;
+#pragma unroll
+    for (int k = 0; k < L; k++) top = w[k] ? k : top;
+    MP<L> r = mp_zero<L>();
+    if (top >= 0) {
+        uint32_t tw = 0;
+#pragma unroll
+        for (int k = 0; k < L; k++) tw = (k == top) ? w[k] : tw;
+        const int32_t z = 32 * (L - 1 - top) + (int32_t)__builtin_clz(tw);   // leading zeros of W
+        const int32_t q = z >> 5;
+        const uint32_t b = (uint32_t)z & 31u;
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            uint32_t hi = 0, lo = 0;
+#pragma unroll
+            for (int t = 0; t < L; t++) {
+                hi = (t == k - q) ? w[t] : hi;
+                lo = (t == k - q - 1) ? w[t] : lo;
+            }
+            r.m[k] = b ? funnel(hi, lo, 32u - b) : hi;
+        }
+        r.e = -z;
+        r.s = (h >> 7) & 1u;
+    }
+    store<L>(X, ps, i * ld + j, r);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -262,13 +289,15 @@ hipError_t launch_fill_i32(int32_t* X, int64_t count, int32_t value, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ps, int64_t count, uint32_t seed, hipStream_t s)
+hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ld, int64_t ps, int64_t rows, int64_t cols, uint64_t seed,
+                               hipStream_t s)
 {
-    const dim3 g((unsigned)((count + 255) / 256));
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 g((unsigned)((rows * cols + 255) / 256));
     switch (L) {
-    case 4: hipLaunchKernelGGL((k_fill_uniform<4>), g, dim3(256), 0, s, X, ps, count, seed); break;
-    case 8: hipLaunchKernelGGL((k_fill_uniform<8>), g, dim3(256), 0, s, X, ps, count, seed); break;
-    case 16: hipLaunchKernelGGL((k_fill_uniform<16>), g, dim3(256), 0, s, X, ps, count, seed); break;
+    case 4: hipLaunchKernelGGL((k_fill_uniform<4>), g, dim3(256), 0, s, X, ld, ps, rows, cols, seed); break;
+    case 8: hipLaunchKernelGGL((k_fill_uniform<8>), g, dim3(256), 0, s, X, ld, ps, rows, cols, seed); break;
+    case 16: hipLaunchKernelGGL((k_fill_uniform<16>), g, dim3(256), 0, s, X, ld, ps, rows, cols, seed); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -21,9 +21,10 @@ hipError_t launch_gemm(int L, int kind, const GemmTask* tasks, const int32_t* ti
 hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,
                        const Bases& bs, int64_t grid, hipStream_t s);
 
-// n elements of uniformly distributed p-bit values in (-1, 1) (scratch data
-// of the autotuner; a hash of seed, index and limb)
-hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ps, int64_t count, uint32_t seed, hipStream_t s);
+// rows x cols seeded p-bit values uniform on (-1, 1) (a hash of seed, element
+// index and limb)
+hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ld, int64_t ps, int64_t rows, int64_t cols, uint64_t seed,
+                               hipStream_t s);
 
 // X[0 .. count) = value (int32); used instead of a memset so captured
 // sequences hold kernels only

@@ -12,13 +12,13 @@ namespace {
 template <int L>
 __device__ __forceinline__ MP<L> ldm(const Bases& bs, const MatRef& r, int64_t i, int64_t j)
 {
-    return load<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j);
+    return load<L>(base_ptr(bs, r.base) + r.off, r.ps, i * r.ld + j);
 }
 
 template <int L>
 __device__ __forceinline__ void stm(const Bases& bs, const MatRef& r, int64_t i, int64_t j, const MP<L>& v)
 {
-    store<L>(bs.p[r.base] + r.off, r.ps, i * r.ld + j, v);
+    store<L>(base_ptr(bs, r.base) + r.off, r.ps, i * r.ld + j, v);
 }
 
 constexpr int PIV_THREADS = 1024;
@@ -101,7 +101,7 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
         if (is_zero<L>(ldm<L>(bs, a, r, c)) && info[0] == 0) info[0] = (int32_t)(c + 1);
     }
     if (r != c) {
-        uint32_t* p = bs.p[a.base] + a.off;
+        uint32_t* p = base_ptr(bs, a.base) + a.off;
         const int64_t w = je - j0;
         for (int64_t e = tid; e < w * (L + 2); e += PIV_THREADS) {
             const int64_t j = j0 + e % w, q = e / w;
@@ -166,7 +166,7 @@ k_lu_swap(Bases bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0, int64
     if (j >= col1) return;
     const int64_t r = piv[c];
     if (r == c) return;
-    uint32_t* p = bs.p[a.base] + a.off;
+    uint32_t* p = base_ptr(bs, a.base) + a.off;
 #pragma unroll
     for (int k = 0; k < L + 2; k++) {
         uint32_t* x = p + k * a.ps + c * a.ld + j;
@@ -209,7 +209,7 @@ k_lu_laswp(Bases bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1, int64
 {
     const int64_t j = col0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= col1) return;
-    uint32_t* p = bs.p[a.base] + a.off;
+    uint32_t* p = base_ptr(bs, a.base) + a.off;
     for (int64_t k = k0; k < k1; k++) {
         const int64_t r = piv[k];
         if (r == k) continue;

@@ -214,15 +214,11 @@ int64_t gemm_tiles(const GemmTask& t)
 
 }  // namespace
 
-void build_plan(Plan& P, const PlanKey& k)
-{
-    P.key = k;
-    Builder b(k);
-    MatRef A{BASE_A, 0, 0, k.lda, k.psa};
-    MatRef B{BASE_B, 0, 0, k.ldb, k.psb};
-    MatRef C{BASE_C, 0, 0, k.ldc, k.psc};
-    b.rec(A, B, C, k.m, k.l, k.n, 0);
+namespace {
 
+void assemble(Plan& P, Builder& b)
+{
+    const PlanKey& k = P.key;
     auto add_node_step = [&](std::vector<NodeTask>& v, int op) {
         if (v.empty()) return;
         Step s{1, op, (int64_t)P.node.size(), (int64_t)v.size(), (int64_t)P.tiles.size(), 0};
@@ -273,6 +269,40 @@ void build_plan(Plan& P, const PlanKey& k)
     P.n_addsub = b.n_addsub;
 }
 
+}  // namespace
+
+void build_plan(Plan& P, const PlanKey& k)
+{
+    P.key = k;
+    Builder b(k);
+    MatRef A{BASE_A, 0, 0, k.lda, k.psa};
+    MatRef B{BASE_B, 0, 0, k.ldb, k.psb};
+    MatRef C{BASE_C, 0, 0, k.ldc, k.psc};
+    b.rec(A, B, C, k.m, k.l, k.n, 0);
+    assemble(P, b);
+    P.base_words = {(int64_t)(k.L + 2) * k.psa, (int64_t)(k.L + 2) * k.psb, (int64_t)(k.L + 2) * k.psc, P.ws_words};
+}
+
+void build_plan_batched(Plan& P, const PlanKey& k, const std::vector<BatchItem>& items)
+{
+    P.key = k;
+    Builder b(k);
+    P.base_words.assign(NBASES, 0);
+    for (size_t r = 0; r < items.size(); r++) {
+        const BatchItem& it = items[r];
+        const int32_t a = NBASES + 3 * (int32_t)r;
+        MatRef A{a, 0, 0, it.lda, it.psa};
+        MatRef B{a + 1, 0, 0, it.ldb, it.psb};
+        MatRef C{a + 2, 0, 0, it.ldc, it.psc};
+        b.rec(A, B, C, it.m, it.l, it.n, 0);
+        P.base_words.push_back((int64_t)(k.L + 2) * it.psa);
+        P.base_words.push_back((int64_t)(k.L + 2) * it.psb);
+        P.base_words.push_back((int64_t)(k.L + 2) * it.psc);
+    }
+    assemble(P, b);
+    P.base_words[BASE_WS] = P.ws_words;
+}
+
 namespace {
 
 // largest word index touched by a rows x cols view (all L + 2 planes), or -1
@@ -282,10 +312,10 @@ int64_t extent(const MatRef& r, int64_t rows, int64_t cols, int L)
     return r.off + (int64_t)(L + 1) * r.ps + (rows - 1) * r.ld + (cols - 1);
 }
 
-bool view_ok(const MatRef& r, int64_t rows, int64_t cols, int L, const int64_t* size)
+bool view_ok(const MatRef& r, int64_t rows, int64_t cols, int L, const int64_t* size, int32_t nb)
 {
     if (rows <= 0 || cols <= 0) return true;
-    if (r.base < 0 || r.base >= NBASES || r.off < 0 || r.ld < cols || r.ps < (rows - 1) * r.ld + cols) return false;
+    if (r.base < 0 || r.base >= nb || r.off < 0 || r.ld < cols || r.ps < (rows - 1) * r.ld + cols) return false;
     return extent(r, rows, cols, L) < size[r.base];
 }
 
@@ -293,15 +323,11 @@ bool view_ok(const MatRef& r, int64_t rows, int64_t cols, int L, const int64_t* 
 
 bool validate_plan(const Plan& P, const char** why)
 {
-    const PlanKey& k = P.key;
-    const int L = k.L;
-    int64_t size[NBASES];
-    size[BASE_A] = (int64_t)(L + 2) * k.psa;
-    size[BASE_B] = (int64_t)(L + 2) * k.psb;
-    size[BASE_C] = (int64_t)(L + 2) * k.psc;
-    size[BASE_WS] = P.ws_words;
+    const int L = P.key.L;
+    const int64_t* size = P.base_words.data();
+    const int32_t nb = (int32_t)P.base_words.size();
     for (const GemmTask& t : P.gemm) {
-        if (!view_ok(t.A, t.m, t.l, L, size) || !view_ok(t.B, t.l, t.n, L, size) || !view_ok(t.C, t.m, t.n, L, size)) {
+        if (!view_ok(t.A, t.m, t.l, L, size, nb) || !view_ok(t.B, t.l, t.n, L, size, nb) || !view_ok(t.C, t.m, t.n, L, size, nb)) {
             *why = "gemm task out of bounds";
             return false;
         }
@@ -322,9 +348,9 @@ bool validate_plan(const Plan& P, const char** why)
             default: *why = "unknown node op"; return false;
             }
             for (int i = 0; i < nin; i++)
-                if (!view_ok(t.in[i], irows, icols, L, size)) { *why = "node input out of bounds"; return false; }
+                if (!view_ok(t.in[i], irows, icols, L, size, nb)) { *why = "node input out of bounds"; return false; }
             for (int i = 0; i < nout; i++)
-                if (!view_ok(t.out[i], t.rows, t.cols, L, size)) { *why = "node output out of bounds"; return false; }
+                if (!view_ok(t.out[i], t.rows, t.cols, L, size, nb)) { *why = "node output out of bounds"; return false; }
         }
     }
     for (const Step& s : P.steps) {

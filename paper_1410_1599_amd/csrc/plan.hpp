@@ -57,6 +57,7 @@ struct Plan {
     std::vector<int32_t> tiles;     // tile -> task index (into gemm or node, per step)
     std::vector<Step> steps;
     int64_t ws_words = 0;           // workspace size in uint32 words
+    std::vector<int64_t> base_words;  // extent in words of every base id (for validation)
     int depth = 0;
     // operation counts of the plan (scalar MP multiplies and adds/subs)
     double n_mul = 0, n_addsub = 0;
@@ -68,6 +69,17 @@ struct Plan {
 
 // Build the host side of a plan (no device allocation).
 void build_plan(Plan& P, const PlanKey& k);
+
+// One product of a batch: shapes and strides; its operands are base ids
+// 4 + 3r (A), 5 + 3r (B), 6 + 3r (C) for item r.
+struct BatchItem {
+    int64_t m, l, n, lda, psa, ldb, psb, ldc, psc;
+};
+
+// All products of a batch in one plan: the passes of a recursion level of
+// every item share a launch, and all leaves of all items share one.  k gives
+// L, algo, cutoff, policy and leaf; its shape fields are unused.
+void build_plan_batched(Plan& P, const PlanKey& k, const std::vector<BatchItem>& items);
 
 // Check that every element any task of the plan touches lies inside its
 // buffer: the caller's A, B, C spanning (L + 2) * ps words from their base

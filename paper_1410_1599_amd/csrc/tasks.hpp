@@ -6,15 +6,24 @@
 // caller pointer.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace mpg {
 
 enum BaseId : int32_t { BASE_A = 0, BASE_B = 1, BASE_C = 2, BASE_WS = 3, NBASES = 4 };
 
+// base pointers of a launch: ids 0..3 inline, ids >= 4 in a device table
+// (the operands of a batched launch)
 struct Bases {
     uint32_t* p[NBASES];
+    uint32_t* const* ext;
 };
+
+__host__ __device__ inline uint32_t* base_ptr(const Bases& b, int32_t id)
+{
+    return id < NBASES ? b.p[id] : b.ext[id - NBASES];
+}
 
 // element (i, j), limb k of a matrix view: p[base][off + k * ps + i * ld + j];
 // the exponent is "limb" L and the sign "limb" L + 1

@@ -32,6 +32,10 @@ class MPError(RuntimeError):
 
 
 def _load():
+    # torch first: its HIP runtime is then the one the library binds to (its
+    # libamdhip64 dependency resolves to the copy torch already loaded), so
+    # torch's allocations and streams are valid inside the library
+    import torch  # noqa: F401
     if not os.path.exists(LIBPATH):
         raise ImportError("libmpgemm.so is not built (run python -m paper_1410_1599_amd.build)")
     lib = ctypes.CDLL(LIBPATH)
@@ -57,6 +61,8 @@ def _load():
         "mp_profile": ([i32], i32),
         "mp_gemm_slice": ([i64, i64, i64, i32, i32] + mat * 3 + [i32p], i32),
         "mp_set_graph_mode": ([i32], i32),
+        "mp_fill_uniform": ([i64, i64, i32, vp, i64, i64, ctypes.c_uint64], i32),
+        "mp_gemm_batched": ([i32, i64p, i64p, i64p, i32, i32, i32] + [ctypes.POINTER(vp), i64p, i64p] * 3, i32),
         "mp_tune": ([i64, i64, i64, i32, i32, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float)], i32),
         "mp_auto_choice": ([i64, i64, i64, i32, i32p, i32p, i32p], i32),
         "mp_tune_save": ([ctypes.c_char_p], i32),
@@ -254,3 +260,25 @@ def mp_lu_async(n, prec, A, piv, info_dev, panel=64, algo=WINOGRAD, cutoff=32, p
     pa, lda, psa = _mat(A)
     return _check(lib.mp_lu_async(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()),
                                   ctypes.c_void_p(info_dev.data_ptr()), int(panel), int(algo), int(cutoff), int(policy)))
+
+
+def mp_gemm_batched(prec, algo, cutoff, As, Bs, Cs):
+    """C_r := A_r B_r for every r, one grouped plan (lists of plane tensors)."""
+    mp_set_stream()
+    k = len(As)
+    I64 = ctypes.c_int64 * k
+    P = ctypes.c_void_p * k
+    mats = [[_mat(t) for t in X] for X in (As, Bs, Cs)]
+    m = I64(*[t.shape[1] for t in As])
+    l = I64(*[t.shape[2] for t in As])
+    n = I64(*[t.shape[2] for t in Bs])
+    args = []
+    for X in mats:
+        args += [P(*[x[0] for x in X]), I64(*[x[1] for x in X]), I64(*[x[2] for x in X])]
+    return _check(lib.mp_gemm_batched(k, m, l, n, prec, int(algo), int(cutoff), *args))
+
+
+def mp_fill_uniform(rows, cols, prec, X, seed):
+    mp_set_stream()
+    px, ld, ps = _mat(X)
+    return _check(lib.mp_fill_uniform(rows, cols, prec, px, ld, ps, ctypes.c_uint64(seed & ((1 << 64) - 1))))
