@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--slice-steps", type=int, default=3, help="timed steps of the INT8-slice path (0: skip)")
+    ap.add_argument("--lu", type=int, default=1, help="run the LU workload (n=512, 512 bits, panel 64, Winograd "
+                                                     "cutoff 32, random and Hilbert inputs); 0: skip")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving run (0: skip): Poisson arrivals at 0.8 x the measured "
                          "saturated rate, 90%% products / 10%% LU solves, 128/256/512 bits")
@@ -67,7 +69,7 @@ def main():
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda").fill_(1)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)          # reads and writes copy_probe_mib MiB each, kernel named "neg"
         torch.cuda.synchronize()
         del src, dst
 
@@ -174,6 +176,43 @@ def main():
         }
         del dS
 
+    lu_res = None
+    if args.lu:
+        lu_res = {}
+        pl, nl = 512, 512
+        for kind in ("random", "hilbert"):
+            Ah = I.uniform_pm1(nl, nl, pl, 5) if kind == "random" else I.hilbert(nl, pl)
+            ones = mp.to_device(I.ones_column(nl, pl))
+            dAl = mp.to_device(Ah)
+            dx = mp.empty(nl, 1, pl)
+            piv = torch.zeros(nl, dtype=torch.int32, device="cuda")
+            mp.mp_gemm(nl, nl, 1, pl, mp.SIMPLE, 0, dAl, ones, dx)          # b = A * ones
+            work = dAl.clone()
+            mp.mp_lu_ex(nl, pl, work, piv, 64, mp.WINOGRAD, 32)              # warm plans
+            work.copy_(dAl)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = mp.mp_lu_ex(nl, pl, work, piv, 64, mp.WINOGRAD, 32)
+            torch.cuda.synchronize()
+            t_lu = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            mp.mp_lu_solve(nl, pl, work, piv, dx)
+            torch.cuda.synchronize()
+            t_solve = time.perf_counter() - t0
+            rec = {"info": info, "lu_ms": round(t_lu * 1e3, 2), "solve_ms": round(t_solve * 1e3, 2),
+                   "lu_rate_flopequiv_per_s": (2.0 * nl ** 3 / 3) / t_lu}
+            if not args.no_cpu:
+                from fractions import Fraction
+                from oracle import cref, mpnum
+                F = mp.to_host(work)
+                pv = piv.cpu().numpy()
+                l2, val = cref.lu_residual(Ah, F, pv, pl)
+                xh = mp.to_host(dx)
+                err = max(abs(mpnum.to_fraction(I.entry(xh, i, 0, pl), pl) - 1) for i in range(nl))
+                rec.update({"residual": val, "residual_log2": round(l2, 2), "max_abs_x_minus_1": float(err)})
+            lu_res[kind] = rec
+        lu_res["config"] = "n=512 prec=512 panel=64 winograd cutoff=32, b = A*ones; residual ||PA-LU||/||A|| (inf)"
+
     serve_res = None
     if args.serve_requests > 0:
         del dA, dB, dC
@@ -218,7 +257,7 @@ def main():
                                "seeds 6/7" % (n, p, args.algo, args.cutoff),
                    "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others, "slice": slice_res,
-        "serve": serve_res,
+        "serve": serve_res, "lu": lu_res,
     }
     print(json.dumps(out))
 

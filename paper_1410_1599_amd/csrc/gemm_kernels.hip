@@ -18,10 +18,42 @@
 
 namespace mpg {
 
+// Base pointers come from a table in memory; read through vector loads they
+// would count as per-lane values.  They are the same in every lane (one task
+// per workgroup), so move them to scalar registers.
+__device__ __forceinline__ uint32_t* wave_uniform(uint32_t* p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (uint32_t*)(((uint64_t)hi << 32) | lo);
+}
+
 template <int L>
 __device__ __forceinline__ const uint32_t* ref_ptr(const Bases& b, const MatRef& r)
 {
-    return base_ptr(b, r.base) + r.off;
+    return wave_uniform(base_ptr(b, r.base)) + r.off;
+}
+
+// Word idx of a plane whose base is the same in every lane, for planes of
+// fewer than 2^30 words: a global load with the base in scalar registers and
+// a 32-bit lane offset, so the address costs no vector arithmetic per limb.
+__device__ __forceinline__ uint32_t ld_plane(const uint32_t* base, uint32_t idx)
+{
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) uint32_t gu32;
+    return *(gu32*)((gchar*)base + idx * 4u);
+}
+
+template <int L>
+__device__ __forceinline__ MP<L> load_planes(const uint32_t* base, int64_t ps, uint32_t idx)
+{
+    MP<L> x;
+#pragma unroll
+    for (int q = 0; q < L; q++) x.m[q] = ld_plane(base + q * ps, idx);
+    x.e = (int32_t)ld_plane(base + L * ps, idx);
+    x.s = ld_plane(base + (L + 1) * ps, idx);
+    return x;
 }
 
 // ------------------------------------------------------------------ Simple
@@ -40,14 +72,29 @@ k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ ti
         const int64_t i = (lt / tn) * tr + (threadIdx.x >> T.tcl);
         const int64_t j = (lt % tn) * tc + (threadIdx.x & (tc - 1));
         if (i >= T.m || j >= T.n) continue;
-        const uint32_t* A = ref_ptr<L>(bs, T.A) + i * T.A.ld;
-        const uint32_t* B = ref_ptr<L>(bs, T.B) + j;
-        uint32_t* C = base_ptr(bs, T.C.base) + T.C.off + i * T.C.ld + j;
+        uint32_t* C = wave_uniform(base_ptr(bs, T.C.base)) + T.C.off + i * T.C.ld + j;
         MP<L> c = T.accum ? load<L>(C, T.C.ps, 0) : mp_zero<L>();
-        for (int k = 0; k < T.l; k++) {
-            const MP<L> a = load<L>(A, T.A.ps, k);
-            const MP<L> b = load<L>(B, T.B.ps, (int64_t)k * T.B.ld);
-            c = add_rn<L>(c, mul_rn<L>(a, b));
+        if (T.A.ps < (1 << 30) && T.B.ps < (1 << 30)) {
+            // every offset inside a plane fits 32 bits
+            const uint32_t* A = ref_ptr<L>(bs, T.A);
+            const uint32_t* B = ref_ptr<L>(bs, T.B);
+            const uint32_t oa = (uint32_t)i * (uint32_t)T.A.ld;
+            const uint32_t bld = (uint32_t)T.B.ld;
+            uint32_t ob = (uint32_t)j;
+            for (int k = 0; k < T.l; k++) {
+                const MP<L> a = load_planes<L>(A, T.A.ps, oa + (uint32_t)k);
+                const MP<L> b = load_planes<L>(B, T.B.ps, ob);
+                ob += bld;
+                c = add_rn<L>(c, mul_rn<L>(a, b));
+            }
+        } else {
+            const uint32_t* A = ref_ptr<L>(bs, T.A) + i * T.A.ld;
+            const uint32_t* B = ref_ptr<L>(bs, T.B) + j;
+            for (int k = 0; k < T.l; k++) {
+                const MP<L> a = load<L>(A, T.A.ps, k);
+                const MP<L> b = load<L>(B, T.B.ps, (int64_t)k * T.B.ld);
+                c = add_rn<L>(c, mul_rn<L>(a, b));
+            }
         }
         store<L>(C, T.C.ps, 0, c);
     }

@@ -65,6 +65,39 @@ __device__ __forceinline__ void mac(uint64_t& acc, uint32_t& c2, uint32_t a, uin
     asm volatile("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(c2), "=s"(unused) : "s"(cy));
 }
 
+// the first product of a column: c2 starts from the carry of this product
+__device__ __forceinline__ void mac_first(uint64_t& acc, uint32_t& c2, uint32_t a, uint32_t b)
+{
+    uint64_t cy, unused;
+    asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(cy) : "v"(a), "v"(b));
+    asm volatile("v_addc_co_u32_e64 %0, %1, 0, 0, %2" : "=v"(c2), "=s"(unused) : "s"(cy));
+}
+
+// acc = a * b (no carry out)
+__device__ __forceinline__ void mac_init(uint64_t& acc, uint32_t a, uint32_t b)
+{
+    uint64_t unused;
+    asm volatile("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(acc), "=s"(unused) : "v"(a), "v"(b));
+}
+
+// M_a < M_b for L-limb mantissas: one subtract-with-borrow chain whose final
+// borrow is the answer (the compiler's own lowering of the unused differences
+// is a compare per limb and a scalar mask chain)
+template <int L>
+__device__ __forceinline__ bool mant_less(const uint32_t* a, const uint32_t* b)
+{
+    uint64_t bw;
+    uint32_t d;
+    asm volatile("v_sub_co_u32_e64 %0, %1, %2, %3" : "=v"(d), "=s"(bw) : "v"(a[0]), "v"(b[0]));
+#pragma unroll
+    for (int k = 1; k < L; k++)
+        asm volatile("v_subb_co_u32_e64 %0, %1, %2, %3, %1" : "=v"(d), "+s"(bw) : "v"(a[k]), "v"(b[k]));
+    (void)d;
+    uint32_t r;                               // this lane's bit of the borrow mask
+    asm volatile("v_cndmask_b32_e64 %0, 0, 1, %1" : "=v"(r) : "s"(bw));
+    return r != 0;
+}
+
 template <int L>
 __device__ __forceinline__ MP<L> mp_zero()
 {
@@ -159,10 +192,15 @@ __device__ __forceinline__ MP<L> mul_rn(const MP<L>& a, const MP<L>& b)
         uint32_t c2 = 0;
 #pragma unroll
         for (int t = L - 2; t <= 2 * L - 2; t++) {
+            bool first = true;
 #pragma unroll
             for (int i = 0; i < L; i++) {
                 const int j = t - i;
-                if (j >= 0 && j < L) mac(acc, c2, a.m[i], b.m[j]);
+                if (j < 0 || j >= L) continue;
+                if (first && t == L - 2) mac_init(acc, a.m[i], b.m[j]);
+                else if (first) mac_first(acc, c2, a.m[i], b.m[j]);
+                else mac(acc, c2, a.m[i], b.m[j]);
+                first = false;
             }
             H[t - (L - 2)] = (uint32_t)acc;
             acc = (acc >> 32) | ((uint64_t)c2 << 32);
@@ -208,21 +246,56 @@ __device__ __forceinline__ MP<L> mul_rn(const MP<L>& a, const MP<L>& b)
 
 // ------------------------------------------------------------------ add
 
+// T[0..L] = (M * 2^32) >> r for r in [0, 31] (exact: nothing leaves the
+// bottom of the guard limb)
+template <int L>
+__device__ __forceinline__ void align_bits(const uint32_t* m, uint32_t r, uint32_t* T)
+{
+    T[0] = funnel(m[0], 0u, r);
+#pragma unroll
+    for (int k = 1; k < L; k++) T[k] = funnel(m[k], m[k - 1], r);
+    T[L] = m[L - 1] >> r;
+}
+
+// (X * 2^32 + (T ^ mk) + (mk & 1)): the guard-limb sum or difference,
+// carry out in c
+template <int L>
+__device__ __forceinline__ void add_window(const uint32_t* xm, const uint32_t* T, uint32_t mk, uint32_t* R,
+                                           uint32_t& c)
+{
+    c = mk & 1u;
+    R[0] = addc(0u, T[0] ^ mk, c, &c);
+#pragma unroll
+    for (int k = 1; k <= L; k++) R[k] = addc(xm[k - 1], T[k] ^ mk, c, &c);
+}
+
+// any of the low s bits of the L-limb mantissa m set (s < 32 L)
+template <int L>
+__device__ __forceinline__ bool lost_bits(const uint32_t* m, uint32_t s)
+{
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+        const uint32_t lo = 32u * k;
+        const uint32_t mask = s >= lo + 32u ? 0xffffffffu : (s > lo ? (1u << (s - lo)) - 1u : 0u);
+        acc |= m[k] & mask;
+    }
+    return acc != 0;
+}
+
 // RN(x + y).  Works on an (L+1)-limb extension R = |X| * 2^32 of the larger
-// operand: a guard limb under the mantissa.  The smaller operand is shifted
-// right by the exponent gap d; bits shifted below the guard limb are ORed into
-// its lowest bit ("sticky jamming"), which cannot move the result across a
-// rounding boundary because the rounding position stays 31 or more bits above
-// bit 0.  A gap below 32 shifts nothing out (the guard limb takes it), the
-// common case; larger gaps take a limb-shift path.
+// operand: a guard limb under the mantissa.  The smaller operand Y is shifted
+// right by the exponent gap d.  A gap below 32 shifts nothing out of the
+// guard limb (the common case, a funnel shift per limb); when any lane of the
+// wave has a larger gap, the whole wave takes a general path (whole-limb
+// shift in binary stages).  The bits of Y that fall below the guard limb are
+// not carried along: they can only decide an exact tie in R, which the
+// rounding step detects and resolves from Y directly.
 template <int L>
 __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
 {
     const bool zx = is_zero(x), zy = is_zero(y);
-    uint32_t bw = 0;
-#pragma unroll
-    for (int k = 0; k < L; k++) (void)subb(x.m[k], y.m[k], bw, &bw);   // bw: M_y > M_x
-    const bool ygt = (y.e > x.e) || (y.e == x.e && bw);
+    const bool ygt = (y.e > x.e) || (y.e == x.e && mant_less<L>(x.m, y.m));
     const bool sw = zy ? false : (zx ? true : ygt);
     const MP<L> X = select(sw, y, x);
     const MP<L> Y = select(sw, x, y);
@@ -230,42 +303,30 @@ __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
     const uint32_t d = yz ? 0u : (uint32_t)(X.e - Y.e);
     const bool subt = X.s != Y.s;
 
-    uint32_t T[L + 1];                        // Y aligned to X's extension
-    if (d < 32u) {
-        T[0] = funnel(Y.m[0], 0u, d);
-#pragma unroll
-        for (int k = 1; k < L; k++) T[k] = funnel(Y.m[k], Y.m[k - 1], d);
-        T[L] = Y.m[L - 1] >> d;
-    } else {
-        uint32_t q = d >> 5, r = d & 31u;
-        if (q > (uint32_t)(L + 1)) { q = L + 1; r = 0; }
-        T[0] = 0;
-#pragma unroll
-        for (int k = 0; k < L; k++) T[k + 1] = Y.m[k];
-        uint32_t st = 0;
+    // T = Y * 2^(32 - d): Y aligned below X's guard limb.  For d < 32 this
+    // is exact.  For larger d the bits of Y below the window are dropped
+    // here; see the rounding step for where they count.
+    uint32_t T[L + 1];
+    if (__builtin_amdgcn_ballot_w64(d >= 32u) == 0) {
+        align_bits<L>(Y.m, d, T);
+    } else {                                  // whole-limb shift by q = d/32, in binary stages
+        const uint32_t dc = d < 32u * (L + 1) ? d : 32u * (L + 1);
+        const uint32_t q = dc >> 5;
+        align_bits<L>(Y.m, dc & 31u, T);
 #pragma unroll
         for (int b = 1; b <= L + 1; b <<= 1) {
-            if (q & (uint32_t)b) {
+            const bool on = (q & (uint32_t)b) != 0;
 #pragma unroll
-                for (int k = 0; k < b && k <= L; k++) st |= T[k];
-#pragma unroll
-                for (int k = 0; k <= L; k++) T[k] = (k + b <= L) ? T[k + b] : 0u;
-            }
+            for (int k = 0; k <= L; k++) T[k] = on ? ((k + b <= L) ? T[k + b] : 0u) : T[k];
         }
-        st |= T[0] & ((1u << r) - 1u);
-#pragma unroll
-        for (int k = 0; k < L; k++) T[k] = funnel(T[k + 1], T[k], r);
-        T[L] >>= r;
-        T[0] |= (st != 0) ? 1u : 0u;
+        if (d >= 32u * (L + 1)) T[0] = 1u;    // Y entirely below the window: a sticky bit
     }
 
     // R = X*2^32 +- T
     const uint32_t mk = subt ? 0xffffffffu : 0u;
     uint32_t R[L + 1];
-    uint32_t c = subt ? 1u : 0u;
-    R[0] = addc(0u, T[0] ^ mk, c, &c);
-#pragma unroll
-    for (int k = 1; k <= L; k++) R[k] = addc(X.m[k - 1], T[k] ^ mk, c, &c);
+    uint32_t c;
+    add_window<L>(X.m, T, mk, R, c);
     int32_t e = X.e;
     if (!subt && c) {                         // sum reached 2^(p+32): shift right once
         const uint32_t lost = R[0] & 1u;
@@ -275,7 +336,8 @@ __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
         R[0] |= lost;
         e += 1;
     }
-    if (subt && R[L] == 0) {                  // cancellation of a whole limb or more
+    const bool deep = subt && (R[L] == 0);    // cancellation of a whole limb or more (rare)
+    if (__builtin_expect(deep, 0)) {
         uint32_t q = 0;
         bool still = true;
 #pragma unroll
@@ -300,10 +362,18 @@ __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
     }
     e -= (int32_t)z;
 
-    // round to the p bits R[1..L]
+    // round to the p bits R[1..L].  When 32 <= d < 32(L+1) the exact sum
+    // differs from R by the dropped bits of Y, less than one unit of R's
+    // bit 0 (added, or taken away for a difference); at most one bit has
+    // cancelled, so the rounding position is bit 30 or above and the dropped
+    // bits decide only an exact tie in R: above it for a sum (round up),
+    // below it for a difference (round down).
     const uint32_t rb = R[0] >> 31;
     const uint32_t st = (R[0] & 0x7fffffffu) ? 1u : 0u;
     uint32_t cu = rb & (st | (R[1] & 1u));
+    if (rb && !st && d >= 32u && d < 32u * (L + 1)) {
+        if (lost_bits<L>(Y.m, d - 32u)) cu = subt ? 0u : 1u;
+    }
     MP<L> r;
 #pragma unroll
     for (int k = 0; k < L; k++) r.m[k] = addc(R[k + 1], 0, cu, &cu);

@@ -43,6 +43,25 @@ def adversarial_pairs(rng, p):
         out.append(((m, 1), (-m, 1)))
         out.append(((m, 1), (-(m - 1 if m > one else m + 1), 1)))
         out.append(((m, 1), (-(m >> 1 | one), 0)))
+    # gaps d = 32 + t past the guard limb where the aligned operand leaves the
+    # guard limb empty below its top two bits, so that the bits shifted out
+    # below the window (present or not) decide a tie or an exact result
+    for t in (1, 2, 5, 31, 32, 33, 64, p - 64, p - 33, p - 32, p - 31, p - 2, p - 1):
+        if t < 1 or t >= p:
+            continue
+        for top2 in (0, 1, 2, 3):
+            for lost in (0, 1, 1 << (t - 1), rng.randrange(1, 1 << t)):
+                my = one | lost
+                if t + 30 < p:
+                    my |= ((top2 & 1) << (t + 30))
+                if t + 31 < p:
+                    my |= ((top2 >> 1) << (t + 31))
+                    my |= (rng.randrange(0, 1 << max(p - t - 32, 1)) << (t + 32)) & (top - ((1 << (t + 32)) - 1))
+                my &= top
+                my |= one
+                for mx in (one, top, rng.randrange(one, 1 << p)):
+                    for s in (1, -1):
+                        out.append(((mx, 7), (s * my, 7 - 32 - t)))
     # zeros
     out.append(((0, 0), (one, 3)))
     out.append(((one, 3), (0, 0)))
