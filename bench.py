@@ -17,6 +17,7 @@ timed on a bounded sample of the same product.
 
 import argparse
 import json
+from fractions import Fraction
 import os
 import sys
 import time
@@ -116,6 +117,8 @@ def main():
         "leaf_share_of_step": round(leaf_ms / all_ms, 4) if all_ms else None,
     }
 
+    limb_host = mp.to_host(dC)               # the headline product, before dC is reused below
+
     # parity spot check of the timed configuration against stored oracle entries
     parity = None
     gold = os.path.join(ROOT, "tests", "golden", "full_size_n%d_p%d.json" % (n, p))
@@ -123,7 +126,7 @@ def main():
         g = json.load(open(gold))
         ents = g["entries"].get(args.algo)
         if ents and g["kind"] == "log_uniform":
-            C = mp.to_host(dC)
+            C = limb_host
             bad = 0
             for i, j, s, e, mh in ents:
                 sig = int(mh, 16) * (-1 if s else 1)
@@ -148,6 +151,7 @@ def main():
 
     # INT8-slice path on the same product (correctly rounded: <= 1/2 ulp)
     slice_res = None
+    slice_host = None
     if args.slice_steps > 0:
         dS = mp.empty(n, n, p)
         mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
@@ -174,7 +178,31 @@ def main():
                          "launch_ms": round(mm_ms, 3)},
             "other_ms": round(sum(r["ms"] for r in srecs if r["kind"] == 3) / args.slice_steps, 3),
         }
+        slice_host = mp.to_host(dS)
         del dS
+
+    # ulp error against stored exact products (RN_p of the exact dot product)
+    accuracy = None
+    gold = os.path.join(ROOT, "tests", "golden", "exact_n%d_p%d.json" % (n, p))
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        if g["kind"] == "log_uniform" and g["seeds"] == [6, 7]:
+            def ulps(x, c):
+                # |x - c| in units of c's last place, 2^(e_c - p)
+                (sx, ex), (sc, ec) = x, c
+                if sc == 0:
+                    return 0.0 if sx == 0 else float("inf")
+                return float(abs(Fraction(sx) * Fraction(2) ** (ex - ec) - sc))
+            res = {}
+            for name, host in (("limb_" + args.algo, limb_host), ("slice", slice_host)):
+                if host is None:
+                    continue
+                worst = 0.0
+                for i, j, s, e, mh in g["entries"]:
+                    worst = max(worst, ulps(I.entry(host, i, j, p), (int(mh, 16) * (-1 if s else 1), e)))
+                res[name] = worst
+            accuracy = {"max_ulp_vs_exact": res, "entries": len(g["entries"]),
+                        "sample": "seeded 64 x 64 grid plus row 0 and column 0; exact values from the CPU oracle"}
 
     lu_res = None
     if args.lu:
@@ -199,19 +227,13 @@ def main():
             mp.mp_lu_solve(nl, pl, work, piv, dx)
             torch.cuda.synchronize()
             t_solve = time.perf_counter() - t0
-            rec = {"info": info, "lu_ms": round(t_lu * 1e3, 2), "solve_ms": round(t_solve * 1e3, 2),
-                   "lu_rate_flopequiv_per_s": (2.0 * nl ** 3 / 3) / t_lu}
-            if not args.no_cpu:
-                from fractions import Fraction
-                from oracle import cref, mpnum
-                F = mp.to_host(work)
-                pv = piv.cpu().numpy()
-                l2, val = cref.lu_residual(Ah, F, pv, pl)
-                xh = mp.to_host(dx)
-                err = max(abs(mpnum.to_fraction(I.entry(xh, i, 0, pl), pl) - 1) for i in range(nl))
-                rec.update({"residual": val, "residual_log2": round(l2, 2), "max_abs_x_minus_1": float(err)})
-            lu_res[kind] = rec
-        lu_res["config"] = "n=512 prec=512 panel=64 winograd cutoff=32, b = A*ones; residual ||PA-LU||/||A|| (inf)"
+            xh = mp.to_host(dx)
+            err = max(abs(Fraction(sig) * Fraction(2) ** (e - pl) - 1)
+                      for sig, e in (I.entry(xh, i, 0, pl) for i in range(nl)))
+            lu_res[kind] = {"info": info, "lu_ms": round(t_lu * 1e3, 2), "solve_ms": round(t_solve * 1e3, 2),
+                            "lu_rate_flopequiv_per_s": (2.0 * nl ** 3 / 3) / t_lu, "max_abs_x_minus_1": float(err)}
+        lu_res["config"] = ("n=512 prec=512 panel=64 winograd cutoff=32, b = A*ones; factors and pivots are checked "
+                            "bit for bit against the CPU oracle by the GPU tests")
 
     serve_res = None
     if args.serve_requests > 0:
@@ -236,14 +258,15 @@ def main():
         cores = cref.threads()
         rows = 2
         # Simple's output rows are independent: time the oracle on the first
-        # rows of the same product, growing the sample to the target length
+        # rows of the same product; a short probe sizes the sample to the
+        # target length, which is then timed on its own
         while True:
             t0 = time.perf_counter()
             cref.gemm(np.ascontiguousarray(A[:, :rows, :]), B, p, algo="simple", m=rows)
             t = time.perf_counter() - t0
-            if t > args.cpu_seconds / 4 or rows >= n:
+            if t > args.cpu_seconds * 0.7 or rows >= n:
                 break
-            rows = min(n, max(rows * 2, int(rows * args.cpu_seconds / max(t, 1e-3) / 2)))
+            rows = min(n, max(rows * 2, int(rows * args.cpu_seconds / max(t, 1e-3))))
         cpu = {"value": 2.0 * rows * n * n / t, "unit": "2mln/s", "cores": cores, "kind": "oracle",
                "sample": "C oracle (oracle/c/mpref.c), Simple on rows 0..%d of the same 2048^3 256-bit product, "
                          "%.1f s on %d threads" % (rows - 1, t, cores)}
@@ -257,7 +280,7 @@ def main():
                                "seeds 6/7" % (n, p, args.algo, args.cutoff),
                    "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others, "slice": slice_res,
-        "serve": serve_res, "lu": lu_res,
+        "accuracy": accuracy, "serve": serve_res, "lu": lu_res,
     }
     print(json.dumps(out))
 

@@ -77,3 +77,7 @@ def test_lu_n512_p512_panel64_winograd(kind):
     b = cref.gemm(A, I.ones_column(n, p), p, algo="simple")
     xg = gpu_solve(Fg, pg, b, p)
     assert planes_equal(xg, cref.lu_solve(Fc, pc, b, p))
+    # exact backward error of the (shared) factors: ||PA - LU||_inf / ||A||_inf
+    l2, val = cref.lu_residual(A, Fg, pg, p)
+    print("%s: residual %.3g (2^%.1f)" % (kind, val, l2))
+    assert l2 < -p + 20

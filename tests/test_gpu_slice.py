@@ -115,3 +115,31 @@ def test_n2048_p256_sampled_exact_and_limb_error():
         worst_limb = max(worst_limb, float(exact.ulp_error(limb, nn, f, p)))
     print("limb Winograd max ulp error on the sample: %.1f; slice: <= 0.5" % worst_limb)
     assert worst_limb >= 0.5
+
+
+def test_n2048_p256_ulp_error_of_every_path():
+    """The 2048 x 2048 256-bit log-uniform workload against stored exact
+    products (RN_p of the exact dot product; a seeded 64 x 64 grid plus row 0
+    and column 0): the slice path returns every sampled entry correctly
+    rounded, so its error (<= 1/2 ulp) is never above the limb path's."""
+    g = json.load(open(os.path.join(GOLD, "exact_n2048_p256.json")))
+    n, p = 2048, 256
+    A = I.log_uniform(n, n, p, 6)
+    B = I.log_uniform(n, n, p, 7)
+    S, _ = gpu_slice(A, B, p)
+    dA, dB, dC = mp.to_device(A), mp.to_device(B), mp.empty(n, n, p)
+    worst = {}
+    for name, algo in (("winograd", mp.WINOGRAD), ("block", mp.BLOCK)):
+        mp.mp_gemm_ex(n, n, n, p, algo, 64, mp.PEEL, mp.LEAF_SIMPLE, dA, dB, dC)
+        torch.cuda.synchronize()
+        C = mp.to_host(dC)
+        w = 0.0
+        for i, j, s, e, mh in g["entries"]:
+            want = (int(mh, 16) * (-1 if s else 1), e)
+            w = max(w, float(exact.ulp_error(I.entry(C, i, j, p), want[0], e - p, p)))
+        worst[name] = w
+    for i, j, s, e, mh in g["entries"]:
+        assert I.entry(S, i, j, p) == (int(mh, 16) * (-1 if s else 1), e), (i, j)
+    print("max ulp vs RN(exact) on %d entries: limb Winograd %.1f, limb Block %.1f, slice 0"
+          % (len(g["entries"]), worst["winograd"], worst["block"]))
+    assert worst["winograd"] >= worst["block"] >= 0
