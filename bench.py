@@ -30,6 +30,34 @@ CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
 INT_LANE_OPS = CUS * SIMDS * LANES * CLOCK_HZ        # 39.3e12 32-bit VALU lane-ops/s
 
 
+def profiled_traffic(path):
+    """HBM bytes per launch of the leaf kernel as measured by rocprofv3
+    FETCH_SIZE / WRITE_SIZE (calibrated on a copy kernel) and recorded in a
+    profile summary; None when there is none or when the kernel sources have
+    changed since (the summary carries their sha256)."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+        if line.startswith("(sha256 over "):
+            fields["files"] = line[len("(sha256 over "):].split(";")[0].rstrip(")\n").split(", ")
+    if not {"traffic_bytes_per_launch", "source_sha256", "files"} <= set(fields):
+        return None
+    h = hashlib.sha256()
+    for f in fields["files"]:
+        fp = os.path.join(ROOT, f.strip())
+        if not os.path.exists(fp):
+            return None
+        h.update(open(fp, "rb").read())
+    if h.hexdigest() != fields["source_sha256"]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,7 +138,9 @@ def main():
     peak = INT_LANE_OPS / 1e12
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-        "frac": round(achieved / peak, 4), "traffic": None,
+        "frac": round(achieved / peak, 4),
+        "traffic": profiled_traffic(os.path.join(ROOT, "profiles", "leaf_gemm_simple_L%d_n%d_p%d_%s.md"
+                                                 % (L, n, p, args.algo))) if args.cutoff == 64 else None,
         "kernel": "k_gemm_simple<L=%d> grouped leaf products" % L,
         "op": "one 32x32->64-bit limb multiply-accumulate; L^2 = %d per MP multiply-add" % (L * L),
         "launch_ms": round(leaf_ms, 3), "units_per_launch": leaf_units,

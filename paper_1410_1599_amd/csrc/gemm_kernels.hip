@@ -56,13 +56,24 @@ __device__ __forceinline__ MP<L> load_planes(const uint32_t* base, int64_t ps, u
     return x;
 }
 
+// Workgroups are handed to the eight XCDs round robin (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  Renumber them so that XCD x walks a
+// contiguous run of tiles: the tiles of one leaf product, which share its B
+// block (and A rows), then meet in one L2 instead of eight.  A bijection of
+// [0, G) for any grid size G.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G)
+{
+    const int64_t q = G >> 3, r = G & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // ------------------------------------------------------------------ Simple
 
 template <int L, int TM>
 __global__ void __launch_bounds__(64 * TM)
 k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
 {
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
         const GemmTask T = tasks[tile_task[t]];
         const int64_t lt = t - T.tile0;
         // a tile is (64 TM / 2^tcl) rows x 2^tcl columns, lanes along a row
@@ -112,7 +123,7 @@ k_gemm_block(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ til
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int nt = 64 * TM;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
         const GemmTask T = tasks[tile_task[t]];
         const int64_t lt = t - T.tile0;
         const int tn = (T.n + 63) >> 6;
