@@ -31,18 +31,11 @@ hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ld, int64_t ps, int64
 hipError_t launch_fill_i32(int32_t* X, int64_t count, int32_t value, hipStream_t s);
 
 // LU building blocks (lu_kernels.hip); the matrix is one MatRef on base A
-hipError_t launch_lu_pivot(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int32_t* piv, int32_t* info,
-                           hipStream_t s);
 hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
                                 int32_t* piv, int32_t* info, hipStream_t s);
 hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, hipStream_t s);
 hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t kb, int64_t je, int64_t n,
                          hipStream_t s);
-hipError_t launch_lu_swap(int L, const Bases& bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0,
-                          int64_t col1, hipStream_t s);
-hipError_t launch_lu_scale(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, hipStream_t s);
-hipError_t launch_lu_rank1(int L, const Bases& bs, MatRef a, int64_t t, int64_t r0, int64_t r1, int64_t c0,
-                           int64_t c1, hipStream_t s);
 hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1,
                            int64_t col0, int64_t col1, int64_t ncols_total, hipStream_t s);
 hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n,

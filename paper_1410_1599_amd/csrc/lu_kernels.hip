@@ -23,47 +23,10 @@ __device__ __forceinline__ void stm(const Bases& bs, const MatRef& r, int64_t i,
 
 constexpr int PIV_THREADS = 1024;
 
-// pivot of column c: the smallest row index i >= c with the largest |a_ic|
-template <int L>
-__global__ void __launch_bounds__(PIV_THREADS)
-k_lu_pivot(Bases bs, MatRef a, int64_t n, int64_t c, int32_t* piv, int32_t* info)
-{
-    __shared__ int32_t sidx[PIV_THREADS];
-    const int tid = threadIdx.x;
-    int32_t best = -1;
-    MP<L> bv = mp_zero<L>();
-    for (int64_t i = c + tid; i < n; i += PIV_THREADS) {
-        const MP<L> v = ldm<L>(bs, a, i, c);
-        if (best < 0 || cmp_abs<L>(v, bv) > 0) {     // ascending scan: ties keep the first
-            best = (int32_t)i;
-            bv = v;
-        }
-    }
-    sidx[tid] = best;
-    __syncthreads();
-    for (int s = PIV_THREADS / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            const int32_t i1 = sidx[tid], i2 = sidx[tid + s];
-            if (i2 >= 0) {
-                if (i1 < 0) {
-                    sidx[tid] = i2;
-                } else {
-                    const int cm = cmp_abs<L>(ldm<L>(bs, a, i2, c), ldm<L>(bs, a, i1, c));
-                    if (cm > 0 || (cm == 0 && i2 < i1)) sidx[tid] = i2;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const int32_t r = sidx[0];
-        piv[c] = r;
-        if (is_zero<L>(ldm<L>(bs, a, r, c)) && info[0] == 0) info[0] = (int32_t)(c + 1);
-    }
-}
-
-// pivot search as above, then the swap of rows c and piv[c] over the panel
-// columns [j0, je) by the same workgroup
+// one workgroup: the pivot of column c is the first row index r >= c of the
+// largest |a_rc| (exact comparison; a tree reduction in LDS, ties to the
+// smaller index); piv[c] = r, info = c + 1 for the first exactly zero pivot;
+// then the same workgroup swaps rows c and r over the panel columns [j0, je)
 template <int L>
 __global__ void __launch_bounds__(PIV_THREADS)
 k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info)
@@ -157,51 +120,6 @@ k_lu_u12(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
     }
 }
 
-// swap rows c and piv[c] over columns [col0, col1)
-template <int L>
-__global__ void __launch_bounds__(256)
-k_lu_swap(Bases bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0, int64_t col1)
-{
-    const int64_t j = col0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= col1) return;
-    const int64_t r = piv[c];
-    if (r == c) return;
-    uint32_t* p = base_ptr(bs, a.base) + a.off;
-#pragma unroll
-    for (int k = 0; k < L + 2; k++) {
-        uint32_t* x = p + k * a.ps + c * a.ld + j;
-        uint32_t* y = p + k * a.ps + r * a.ld + j;
-        const uint32_t t = *x;
-        *x = *y;
-        *y = t;
-    }
-}
-
-// multipliers of column c: a_ic := a_ic / a_cc for i in (c, n)
-template <int L>
-__global__ void __launch_bounds__(256)
-k_lu_scale(Bases bs, MatRef a, int64_t n, int64_t c)
-{
-    const int64_t i = c + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const MP<L> d = ldm<L>(bs, a, c, c);
-    stm<L>(bs, a, i, c, div_rn<L>(ldm<L>(bs, a, i, c), d));
-}
-
-// rank-one update: a_rj := a_rj - a_rt a_tj for r in [r0, r1), j in [c0, c1)
-template <int L>
-__global__ void __launch_bounds__(256)
-k_lu_rank1(Bases bs, MatRef a, int64_t t, int64_t r0, int64_t r1, int64_t c0, int64_t c1)
-{
-    const int64_t w = c1 - c0;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (r1 - r0) * w) return;
-    const int64_t r = r0 + e / w, j = c0 + e % w;
-    const MP<L> l = ldm<L>(bs, a, r, t);
-    const MP<L> u = ldm<L>(bs, a, t, j);
-    stm<L>(bs, a, r, j, sub_rn<L>(ldm<L>(bs, a, r, j), mul_rn<L>(l, u)));
-}
-
 // apply the swaps piv[k0 .. k1) in order to columns [col0, col1)
 template <int L>
 __global__ void __launch_bounds__(256)
@@ -274,13 +192,6 @@ unsigned blocks_for(int64_t n, int per)
     default: return hipErrorInvalidValue;  \
     }
 
-hipError_t launch_lu_pivot(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int32_t* piv, int32_t* info,
-                           hipStream_t s)
-{
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_pivot<LL>), dim3(1), dim3(PIV_THREADS), 0, s, bs, a, n, c, piv, info));
-    return hipGetLastError();
-}
-
 hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
                                 int32_t* piv, int32_t* info, hipStream_t s)
 {
@@ -302,32 +213,6 @@ hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t k
 {
     if (n - je <= 0 || kb <= 1) return hipSuccess;
     MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_u12<LL>), dim3((unsigned)(n - je)), dim3(64), 0, s, bs, a, j0, kb, je));
-    return hipGetLastError();
-}
-
-hipError_t launch_lu_swap(int L, const Bases& bs, MatRef a, int64_t c, const int32_t* piv, int64_t col0,
-                          int64_t col1, hipStream_t s)
-{
-    if (col1 <= col0) return hipSuccess;
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_swap<LL>), dim3(blocks_for(col1 - col0, 256)), dim3(256), 0, s, bs, a,
-                                         c, piv, col0, col1));
-    return hipGetLastError();
-}
-
-hipError_t launch_lu_scale(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, hipStream_t s)
-{
-    if (n - c - 1 <= 0) return hipSuccess;
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_scale<LL>), dim3(blocks_for(n - c - 1, 256)), dim3(256), 0, s, bs, a,
-                                         n, c));
-    return hipGetLastError();
-}
-
-hipError_t launch_lu_rank1(int L, const Bases& bs, MatRef a, int64_t t, int64_t r0, int64_t r1, int64_t c0,
-                           int64_t c1, hipStream_t s)
-{
-    if (r1 <= r0 || c1 <= c0) return hipSuccess;
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_rank1<LL>), dim3(blocks_for((r1 - r0) * (c1 - c0), 256)), dim3(256),
-                                         0, s, bs, a, t, r0, r1, c0, c1));
     return hipGetLastError();
 }
 
