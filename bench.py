@@ -204,7 +204,7 @@ def main():
             "accuracy": "correctly rounded (<= 0.5 ulp vs the exact product); the limb path's per-operation "
                         "rounding is never closer",
             "roofline": {"bound": "mfma", "achieved": round(mm_tops, 2), "peak": 5000.0, "unit": "TOP/s (int8)",
-                         "frac": round(mm_tops / 5000.0, 4), "kernel": "k_slice_gemm (v_mfma_i32_16x16x64_i8)",
+                         "frac": round(mm_tops / 5000.0, 4), "kernel": "k_slice_gemm (v_mfma_i32_32x32x32_i8)",
                          "launch_ms": round(mm_ms, 3)},
             "other_ms": round(sum(r["ms"] for r in srecs if r["kind"] == 3) / args.slice_steps, 3),
         }

@@ -15,7 +15,7 @@ constexpr int SLICE_NWZ4 = 15, SLICE_NWZ8 = 23, SLICE_NWZ16 = 39;
 // |digit| <= 128, so a product is at most 2^14 and an INT32 sum of K of them
 // is exact while K * 2^14 < 2^31
 constexpr int64_t SLICE_KMAX = 131008;
-constexpr int SLICE_TILE_M = 256, SLICE_TILE_N = 128, SLICE_KSTEP = 64;
+constexpr int SLICE_TILE_M = 256, SLICE_TILE_N = 256, SLICE_KSTEP = 64;
 
 struct SliceTask {
     int32_t u;       // diagonal: pairs (s, u - s)

@@ -20,6 +20,7 @@ namespace mpg {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ------------------------------------------------------------------ exponent scan
 
@@ -199,93 +200,138 @@ k_slice_digits(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t o
 
 // ------------------------------------------------------------------ INT8 products
 
-constexpr int TM = SLICE_TILE_M, TN = SLICE_TILE_N, TKK = SLICE_KSTEP, LDSW = TKK + 16;
-constexpr int GT = 512;                            // 8 waves: 4 (rows) x 2 (columns) of 64 x 64
-constexpr int CHA = TM * TKK / 16 / GT;            // 16-byte chunks of A per thread and step
-constexpr int CHB = TN * TKK / 16 / GT;
+constexpr int TM = SLICE_TILE_M, TN = SLICE_TILE_N, TKK = SLICE_KSTEP;
+constexpr int GT = 512;                            // 8 waves: 2 (rows) x 4 (columns) of 128 x 64
+constexpr int WM = 128, WN = 64;                   // wave tile
+constexpr int FA = WM / 32, FB = WN / 32;          // 32 x 32 MFMA blocks per wave: FA x FB
+constexpr int NST = 4;                             // LDS stages in flight
+static_assert(2 * WM == TM && 4 * WN == TN, "wave grid 2 x 4");
+static_assert(TKK == 64 && TM == 256 && TN == 256 && FA == 4 && FB == 2,
+              "the load map and the fragment reads below assume these shapes");
 
-// One workgroup: a 256 x 128 tile of G_slot = sum_{s = s0}^{s1 - 1} A8_s B8_{u-s}^T.
-// The inner loop walks (pair, 64-wide k step); the next step's operands are
-// loaded into registers while the matrix cores work on the current one, then
-// written to the other LDS buffer (one barrier per step).
+// vmcnt(n), n < 64, with the other counters left alone (gfx9 encoding: vmcnt
+// bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+#define SLICE_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15) | (((n) >> 4) << 14))
+
+// LDS holds a stage as 64-byte rows of 4 chunks of 16 bytes; chunk g of row r
+// sits at position g ^ ((r >> 2) & 3), so the 16 rows one MFMA fragment read
+// touches at a time cover all 64 banks.
+
+// LDS byte address of a shared-memory pointer
+__device__ __forceinline__ uint32_t lds_addr(const int8_t* p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) int8_t*)p;
+}
+
+// global_load_lds_dwordx4: each lane's 16 bytes at src go to LDS at
+// lds + 16 * lane.  Issued through asm so that the compiler, which would make
+// every later LDS read wait for all such loads, leaves the waiting to the
+// kernel's explicit vmcnt waits (the instruction has no register result).
+__device__ __forceinline__ void lds_dma16(const int8_t* src, uint32_t lds)
+{
+    asm volatile("s_mov_b32 m0, %1\n\t"
+                 "s_nop 0\n\t"
+                 "global_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(src), "s"(lds)
+                 : "m0", "memory");
+}
+
+// One workgroup: a 256 x 256 tile of G_slot = sum_{s = s0}^{s1 - 1} A8_s B8_{u-s}^T.
+// The inner loop walks (pair, 64-wide k step).  Operands go from global memory
+// straight into LDS (global_load_lds_dwordx4: lane l of a wave writes the 16
+// bytes at wave base + 16 l), NST - 1 steps ahead of the matrix cores; one
+// barrier per step.  A wave's 128 x 64 block is 4 x 2 MFMA blocks of
+// 32 x 32 x 32 (on gfx950 the 32 x 32 x 32 INT8 form issues twice the MACs per
+// cycle of 16 x 16 x 64); it reads 12 KB of LDS per step (1/43 byte per MAC).
 __global__ void __launch_bounds__(GT)
 k_slice_gemm(const SliceTask* __restrict__ tasks, const int8_t* __restrict__ A8, const int8_t* __restrict__ B8,
              int32_t* __restrict__ G, int64_t a_plane, int64_t b_plane, int64_t g_plane, int32_t kpad,
              int32_t npad)
 {
-    __shared__ __attribute__((aligned(16))) int8_t sA[2][TM][LDSW];
-    __shared__ __attribute__((aligned(16))) int8_t sB[2][TN][LDSW];
+    __shared__ __attribute__((aligned(16))) int8_t sA[NST][TM * TKK];
+    __shared__ __attribute__((aligned(16))) int8_t sB[NST][TN * TKK];
     const SliceTask T = tasks[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wy = wave >> 1, wx = wave & 1;
-    v4i acc[4][4];
+    const int wy = wave >> 2, wx = wave & 3;
+    v16i acc[FA][FB];
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < FA; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = (v4i){0, 0, 0, 0};
+        for (int b = 0; b < FB; b++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) acc[a][b][e] = 0;
     const int64_t i0 = (int64_t)T.ti * TM, j0 = (int64_t)T.tj * TN;
     const int ksteps = kpad / TKK;
     const int nsteps = (T.s1 - T.s0) * ksteps;
-    v4i ra[CHA], rb[CHB];
-    auto fetch = [&](int step) {
+    // wave w loads tile rows 32 w .. 32 w + 31 of A and of B, 16 rows per
+    // instruction; lane l brings row l / 4 of the 16, the chunk that belongs
+    // at its LDS position l % 4
+    const int lrow = lane >> 2;
+    const int lchunk = (lane & 3) ^ ((lane >> 4) & 3);
+    auto issue = [&](int step) {
         const int s = T.s0 + step / ksteps;
         const int k0 = (step % ksteps) * TKK;
-        const int8_t* Ap = A8 + (int64_t)s * a_plane + i0 * kpad + k0;
-        const int8_t* Bp = B8 + (int64_t)(T.u - s) * b_plane + j0 * kpad + k0;
+        const int buf = step % NST;
+        const int8_t* Ab = A8 + (int64_t)s * a_plane + (i0 + 32 * wave) * kpad + k0;
+        const int8_t* Bb = B8 + (int64_t)(T.u - s) * b_plane + (j0 + 32 * wave) * kpad + k0;
 #pragma unroll
-        for (int c = 0; c < CHA; c++) {
-            const int q = tid + c * GT;
-            ra[c] = *(const v4i*)(Ap + (int64_t)(q >> 2) * kpad + (q & 3) * 16);
-        }
-#pragma unroll
-        for (int c = 0; c < CHB; c++) {
-            const int q = tid + c * GT;
-            rb[c] = *(const v4i*)(Bp + (int64_t)(q >> 2) * kpad + (q & 3) * 16);
+        for (int b = 0; b < 2; b++) {
+            const int64_t off = (int64_t)(16 * b + lrow) * kpad + 16 * lchunk;
+            lds_dma16(Ab + off, __builtin_amdgcn_readfirstlane(lds_addr(&sA[buf][(32 * wave + 16 * b) * TKK])));
+            lds_dma16(Bb + off, __builtin_amdgcn_readfirstlane(lds_addr(&sB[buf][(32 * wave + 16 * b) * TKK])));
         }
     };
-    auto stash = [&](int buf) {
+    // this lane's fragment rows: A rows wy * 128 + 32 t + (l % 32), B rows
+    // wx * 64 + 32 t + (l % 32); the swizzled chunk depends on l only
+    const int frow = lane & 31;
+    auto compute = [&](int buf) {
+        // all fragments of the step first (48 registers), then its 16 MFMAs
+        v4i af[TKK / 32][FA], bf[TKK / 32][FB];
 #pragma unroll
-        for (int c = 0; c < CHA; c++) {
-            const int q = tid + c * GT;
-            *(v4i*)&sA[buf][q >> 2][(q & 3) * 16] = ra[c];
-        }
+        for (int h = 0; h < TKK / 32; h++) {         // 32-deep MFMA slices of the step
+            // lane l holds row (col) l % 32 of the block, bytes 16 (l / 32) .. +16 of the slice
+            const int pos = 16 * ((2 * h + (lane >> 5)) ^ ((lane >> 2) & 3));
 #pragma unroll
-        for (int c = 0; c < CHB; c++) {
-            const int q = tid + c * GT;
-            *(v4i*)&sB[buf][q >> 2][(q & 3) * 16] = rb[c];
+            for (int t = 0; t < FA; t++) af[h][t] = *(const v4i*)&sA[buf][(wy * WM + 32 * t + frow) * TKK + pos];
+#pragma unroll
+            for (int t = 0; t < FB; t++) bf[h][t] = *(const v4i*)&sB[buf][(wx * WN + 32 * t + frow) * TKK + pos];
         }
+        __builtin_amdgcn_sched_barrier(0);           // keep the reads ahead of the MFMAs
+#pragma unroll
+        for (int h = 0; h < TKK / 32; h++)
+#pragma unroll
+            for (int a = 0; a < FA; a++)
+#pragma unroll
+                for (int b = 0; b < FB; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[h][a], bf[h][b], acc[a][b], 0, 0, 0);
     };
-    if (nsteps > 0) {
-        fetch(0);
-        stash(0);
-    }
-    __syncthreads();
+    // 4 load instructions per wave and step: step t may proceed once at most
+    // 4 min(NST - 2, nsteps - 1 - t) of this wave's loads are outstanding.
+    // The barrier is a bare s_barrier (asm, so no memory access moves across
+    // it): every wave has waited for its own loads, and its reads of stage
+    // t - 1 have completed (the matrix cores consumed them), so after it
+    // stage t is in LDS and stage t - 1 may be overwritten.
+    for (int st = 0; st < NST - 1 && st < nsteps; st++) issue(st);
     for (int step = 0; step < nsteps; step++) {
-        const int buf = step & 1;
-        if (step + 1 < nsteps) fetch(step + 1);
-        v4i af[4], bf[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-            af[t] = *(const v4i*)&sA[buf][wy * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
-            bf[t] = *(const v4i*)&sB[buf][wx * 64 + t * 16 + (lane & 15)][(lane >> 4) * 16];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int b = 0; b < 4; b++)
-                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
-        if (step + 1 < nsteps) stash(buf ^ 1);
-        __syncthreads();
+        const int later = nsteps - 1 - step;
+        if (later >= 2) SLICE_WAIT_VM(8);
+        else if (later == 1) SLICE_WAIT_VM(4);
+        else SLICE_WAIT_VM(0);
+        asm volatile("s_barrier" ::: "memory");
+        if (step + NST - 1 < nsteps) issue(step + NST - 1);
+        compute(step % NST);
     }
     int32_t* Gp = G + (int64_t)T.slot * g_plane;
+    // output register e of a block is row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < FA; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++)
+        for (int b = 0; b < FB; b++)
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int64_t row = i0 + wy * 64 + a * 16 + 4 * (lane >> 4) + e;
-                const int64_t col = j0 + wx * 64 + b * 16 + (lane & 15);
+            for (int e = 0; e < 16; e++) {
+                const int64_t row = i0 + wy * WM + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                const int64_t col = j0 + wx * WN + b * 32 + (lane & 31);
                 Gp[row * npad + col] = acc[a][b][e];
             }
 }
