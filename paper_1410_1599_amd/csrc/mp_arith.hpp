@@ -287,10 +287,11 @@ __device__ __forceinline__ bool lost_bits(const uint32_t* m, uint32_t s)
 // operand: a guard limb under the mantissa.  The smaller operand Y is shifted
 // right by the exponent gap d.  A gap below 32 shifts nothing out of the
 // guard limb (the common case, a funnel shift per limb); when any lane of the
-// wave has a larger gap, the whole wave takes a general path (whole-limb
-// shift in binary stages).  The bits of Y that fall below the guard limb are
-// not carried along: they can only decide an exact tie in R, which the
-// rounding step detects and resolves from Y directly.
+// wave has a larger gap, the whole wave takes a whole-limb shift in binary
+// stages (two stages while every gap is below 128, all of them otherwise).
+// The bits of Y that fall below the guard limb are not carried along: they
+// can only decide an exact tie in R, which the rounding step detects and
+// resolves from Y directly.
 template <int L>
 __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
 {
@@ -309,6 +310,16 @@ __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
     uint32_t T[L + 1];
     if (__builtin_amdgcn_ballot_w64(d >= 32u) == 0) {
         align_bits<L>(Y.m, d, T);
+    } else if (__builtin_amdgcn_ballot_w64(d >= 128u) == 0) {
+        // gaps below 128: whole-limb shifts by q = d/32 <= 3, two stages
+        const uint32_t q = d >> 5;
+        align_bits<L>(Y.m, d & 31u, T);
+#pragma unroll
+        for (int b = 1; b <= 2; b <<= 1) {
+            const bool on = (q & (uint32_t)b) != 0;
+#pragma unroll
+            for (int k = 0; k <= L; k++) T[k] = on ? ((k + b <= L) ? T[k + b] : 0u) : T[k];
+        }
     } else {                                  // whole-limb shift by q = d/32, in binary stages
         const uint32_t dc = d < 32u * (L + 1) ? d : 32u * (L + 1);
         const uint32_t q = dc >> 5;
