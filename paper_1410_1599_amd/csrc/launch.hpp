@@ -36,8 +36,9 @@ hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int
 hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, hipStream_t s);
 hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t kb, int64_t je, int64_t n,
                          hipStream_t s);
+// piv[k0 .. k1) applied in order to the columns [c0, c1) and [c2, c3)
 hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1,
-                           int64_t col0, int64_t col1, int64_t ncols_total, hipStream_t s);
+                           int64_t c0, int64_t c1, int64_t c2, int64_t c3, hipStream_t s);
 hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n,
                            hipStream_t s);
 

@@ -54,8 +54,7 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
             MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, s));
             MPG_TRY(launch_lu_eliminate(L, bs, a, n, c, je, s));
         }
-        MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, n, s));
-        MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, je, n, n, s));
+        MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, je, n, s));
         if (je >= n) break;
         MPG_TRY(launch_lu_u12(L, bs, a, j0, kb, je, n, s));
         const int64_t m2 = n - je;

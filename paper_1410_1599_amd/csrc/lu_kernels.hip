@@ -21,16 +21,19 @@ __device__ __forceinline__ void stm(const Bases& bs, const MatRef& r, int64_t i,
     store<L>(base_ptr(bs, r.base) + r.off, r.ps, i * r.ld + j, v);
 }
 
-constexpr int PIV_THREADS = 1024;
+constexpr int PIV_THREADS = 256;
 
 // one workgroup: the pivot of column c is the first row index r >= c of the
-// largest |a_rc| (exact comparison; a tree reduction in LDS, ties to the
-// smaller index); piv[c] = r, info = c + 1 for the first exactly zero pivot;
-// then the same workgroup swaps rows c and r over the panel columns [j0, je)
+// largest |a_rc| (exact comparison; ties to the smaller index): each thread
+// scans a strided share of the rows keeping its best in registers, then the
+// candidates (value and index) are reduced in LDS.  piv[c] = r, info = c + 1
+// for the first exactly zero pivot; then the same workgroup swaps rows c and
+// r over the panel columns [j0, je)
 template <int L>
 __global__ void __launch_bounds__(PIV_THREADS)
 k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info)
 {
+    __shared__ uint32_t sv[L + 2][PIV_THREADS];
     __shared__ int32_t sidx[PIV_THREADS];
     const int tid = threadIdx.x;
     int32_t best = -1;
@@ -42,18 +45,38 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
             bv = v;
         }
     }
+#pragma unroll
+    for (int q = 0; q < L; q++) sv[q][tid] = bv.m[q];
+    sv[L][tid] = (uint32_t)bv.e;
+    sv[L + 1][tid] = bv.s;
     sidx[tid] = best;
     __syncthreads();
     for (int s = PIV_THREADS / 2; s > 0; s >>= 1) {
         if (tid < s) {
             const int32_t i1 = sidx[tid], i2 = sidx[tid + s];
+            bool take = false;
             if (i2 >= 0) {
                 if (i1 < 0) {
-                    sidx[tid] = i2;
+                    take = true;
                 } else {
-                    const int cm = cmp_abs<L>(ldm<L>(bs, a, i2, c), ldm<L>(bs, a, i1, c));
-                    if (cm > 0 || (cm == 0 && i2 < i1)) sidx[tid] = i2;
+                    MP<L> x1, x2;
+#pragma unroll
+                    for (int q = 0; q < L; q++) {
+                        x1.m[q] = sv[q][tid];
+                        x2.m[q] = sv[q][tid + s];
+                    }
+                    x1.e = (int32_t)sv[L][tid];
+                    x2.e = (int32_t)sv[L][tid + s];
+                    x1.s = sv[L + 1][tid];
+                    x2.s = sv[L + 1][tid + s];
+                    const int cm = cmp_abs<L>(x2, x1);
+                    take = cm > 0 || (cm == 0 && i2 < i1);
                 }
+            }
+            if (take) {
+#pragma unroll
+                for (int q = 0; q < L + 2; q++) sv[q][tid] = sv[q][tid + s];
+                sidx[tid] = i2;
             }
         }
         __syncthreads();
@@ -61,7 +84,7 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
     const int64_t r = sidx[0];
     if (tid == 0) {
         piv[c] = (int32_t)r;
-        if (is_zero<L>(ldm<L>(bs, a, r, c)) && info[0] == 0) info[0] = (int32_t)(c + 1);
+        if (sv[L - 1][0] == 0 && info[0] == 0) info[0] = (int32_t)(c + 1);
     }
     if (r != c) {
         uint32_t* p = base_ptr(bs, a.base) + a.off;
@@ -120,24 +143,70 @@ k_lu_u12(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
     }
 }
 
-// apply the swaps piv[k0 .. k1) in order to columns [col0, col1)
+// Apply the swaps piv[k0 .. k1) in order (k1 - k0 <= LASWP_MAXK) to the
+// columns [c0, c1) and [c2, c3).  The swaps only move the rows k0 .. k1 - 1
+// and the rows they name, so they form one permutation of at most
+// 2 (k1 - k0) "slots": one thread works it out in LDS (src[s] = the slot whose
+// old content ends in slot s), then each workgroup moves the changed slots of
+// one plane and LASWP_CW columns through LDS (all reads before all writes).
+constexpr int LASWP_MAXK = 256, LASWP_MAXS = 2 * LASWP_MAXK, LASWP_CW = 16, LASWP_THREADS = 256;
+
 template <int L>
-__global__ void __launch_bounds__(256)
-k_lu_laswp(Bases bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1, int64_t col0, int64_t col1)
+__global__ void __launch_bounds__(LASWP_THREADS)
+k_lu_laswp(Bases bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1, int64_t c0, int64_t c1, int64_t c2,
+           int64_t c3)
 {
-    const int64_t j = col0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= col1) return;
-    uint32_t* p = base_ptr(bs, a.base) + a.off;
-    for (int64_t k = k0; k < k1; k++) {
-        const int64_t r = piv[k];
-        if (r == k) continue;
-#pragma unroll
-        for (int q = 0; q < L + 2; q++) {
-            uint32_t* x = p + q * a.ps + k * a.ld + j;
-            uint32_t* y = p + q * a.ps + r * a.ld + j;
-            const uint32_t t = *x;
-            *x = *y;
-            *y = t;
+    __shared__ int32_t rowof[LASWP_MAXS], src[LASWP_MAXS];
+    __shared__ uint32_t tile[LASWP_MAXS][LASWP_CW];
+    __shared__ int32_t s_ns;
+    if (threadIdx.x == 0) {
+        const int kb = (int)(k1 - k0);
+        int ns = kb;
+        for (int t = 0; t < kb; t++) {
+            rowof[t] = (int32_t)(k0 + t);
+            src[t] = t;
+        }
+        for (int t = 0; t < kb; t++) {
+            const int64_t r = piv[k0 + t];   // r >= k0 + t by construction of the pivots
+            int sl;
+            if (r < k1) {
+                sl = (int)(r - k0);
+            } else {
+                sl = -1;
+                for (int u = kb; u < ns; u++)
+                    if (rowof[u] == r) sl = u;
+                if (sl < 0) {
+                    sl = ns++;
+                    rowof[sl] = (int32_t)r;
+                    src[sl] = sl;
+                }
+            }
+            const int x = src[t];
+            src[t] = src[sl];
+            src[sl] = x;
+        }
+        s_ns = ns;
+    }
+    __syncthreads();
+    const int ns = s_ns;
+    const int64_t n1 = c1 - c0, nc = n1 + (c3 - c2);
+    const int64_t cb = (int64_t)blockIdx.x * LASWP_CW;
+    uint32_t* P = base_ptr(bs, a.base) + a.off + (int64_t)blockIdx.y * a.ps;
+    for (int e = threadIdx.x; e < ns * LASWP_CW; e += LASWP_THREADS) {
+        const int sl = e / LASWP_CW, jj = e % LASWP_CW;
+        const int64_t ci = cb + jj;
+        if (ci < nc && src[sl] != sl) {
+            const int64_t j = ci < n1 ? c0 + ci : c2 + (ci - n1);
+            tile[sl][jj] = P[(int64_t)rowof[src[sl]] * a.ld + j];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ns * LASWP_CW; e += LASWP_THREADS) {
+        const int sl = e / LASWP_CW, jj = e % LASWP_CW;
+        const int64_t ci = cb + jj;
+        if (ci < nc && src[sl] != sl) {
+            const int64_t j = ci < n1 ? c0 + ci : c2 + (ci - n1);
+            P[(int64_t)rowof[sl] * a.ld + j] = tile[sl][jj];
         }
     }
 }
@@ -217,11 +286,16 @@ hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t k
 }
 
 hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1,
-                           int64_t col0, int64_t col1, int64_t /*ncols_total*/, hipStream_t s)
+                           int64_t c0, int64_t c1, int64_t c2, int64_t c3, hipStream_t s)
 {
-    if (col1 <= col0 || k1 <= k0) return hipSuccess;
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_laswp<LL>), dim3(blocks_for(col1 - col0, 256)), dim3(256), 0, s, bs,
-                                         a, piv, k0, k1, col0, col1));
+    const int64_t nc = (c1 - c0) + (c3 - c2);
+    if (nc <= 0 || k1 <= k0) return hipSuccess;
+    const dim3 g((unsigned)((nc + LASWP_CW - 1) / LASWP_CW), (unsigned)(L + 2));
+    for (int64_t k = k0; k < k1; k += LASWP_MAXK) {
+        const int64_t ke = k + LASWP_MAXK < k1 ? k + LASWP_MAXK : k1;
+        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_laswp<LL>), g, dim3(LASWP_THREADS), 0, s, bs, a, piv, k, ke, c0,
+                                             c1, c2, c3));
+    }
     return hipGetLastError();
 }
 

@@ -440,26 +440,28 @@ __device__ __forceinline__ int cmp_abs(const MP<L>& x, const MP<L>& y)
 // Digit estimate: with R the (L+1)-limb window of the running remainder
 // (R < 2^32 My) and N, D its top three and My's top two limbs, the true digit
 // floor(R / My) and N / D differ by less than 2^-30 plus an integer step,
-// and N / D evaluated in double precision is off by less than 2^-19 (four
-// roundings of values below 2^96 and 2^64, relative 2^-53 each).  So the
-// floor of the double estimate is the digit or one off either way; the
-// multiply-subtract is corrected by adding My back or subtracting it once
-// more (two rounds of each are allowed).
+// and N / D evaluated in double precision as N * (1 / D) is off by less than
+// 2^-18 (five roundings of values below 2^96 and 2^64, relative 2^-53 each,
+// on a quotient below 2^33).  So the floor of the double estimate is the digit
+// or one off either way; the multiply-subtract is corrected by adding My back
+// or subtracting it once more (two rounds of each are allowed).
 template <int L>
 __device__ __forceinline__ MP<L> div_rn(const MP<L>& x, const MP<L>& y)
 {
     static_assert(L >= 3, "the digit estimate needs L >= 3");
     const uint32_t* v = y.m;
     const double D = (double)v[L - 1] * 4294967296.0 + (double)v[L - 2];
+    const double invD = 1.0 / D;
     uint32_t R[L + 1], Q[L + 2];
 #pragma unroll
     for (int k = 0; k < L; k++) R[k] = x.m[k];
     R[L] = 0;
 #pragma unroll
     for (int k = 0; k < L + 2; k++) Q[k] = 0;
+#pragma unroll
     for (int step = 0; step < L + 2; step++) {
         const double N = ((double)R[L] * 4294967296.0 + (double)R[L - 1]) * 4294967296.0 + (double)R[L - 2];
-        double qd = floor(N / D);
+        double qd = floor(N * invD);
         qd = qd > 4294967295.0 ? 4294967295.0 : qd;
         uint32_t qh = (uint32_t)qd;
         // R -= qh * My
@@ -483,18 +485,18 @@ __device__ __forceinline__ MP<L> div_rn(const MP<L>& x, const MP<L>& y)
                 bw = c ? 0u : 1u;
             }
         }
-        // still >= My: subtract once more
+        // still >= My: subtract once more (a second time only if the first
+        // went through)
 #pragma unroll
         for (int it = 0; it < 2; it++) {
             uint32_t b2 = 0, T[L + 1];
 #pragma unroll
             for (int k = 0; k < L; k++) T[k] = subb(R[k], v[k], b2, &b2);
             T[L] = subb(R[L], 0u, b2, &b2);
-            if (!b2) {
+            if (b2) break;
 #pragma unroll
-                for (int k = 0; k <= L; k++) R[k] = T[k];
-                qh += 1;
-            }
+            for (int k = 0; k <= L; k++) R[k] = T[k];
+            qh += 1;
         }
 #pragma unroll
         for (int k = L + 1; k >= 1; k--) Q[k] = Q[k - 1];
