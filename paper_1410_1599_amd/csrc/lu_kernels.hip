@@ -23,22 +23,23 @@ __device__ __forceinline__ void stm(const Bases& bs, const MatRef& r, int64_t i,
 
 constexpr int PIV_THREADS = 256;
 
-// one workgroup: the pivot of column c is the first row index r >= c of the
-// largest |a_rc| (exact comparison; ties to the smaller index): each thread
-// scans a strided share of the rows keeping its best in registers, then the
+// The pivot of column c is the first row index r >= c of the largest |a_rc|
+// (exact comparison; ties to the smaller index): each of the NT threads scans
+// a strided share of the rows keeping its best in registers, then the
 // candidates (value and index) are reduced in LDS.  piv[c] = r, info = c + 1
 // for the first exactly zero pivot; then the same workgroup swaps rows c and
-// r over the panel columns [j0, je)
-template <int L>
-__global__ void __launch_bounds__(PIV_THREADS)
-k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info)
+// r over the panel columns [j0, je).  Called by all NT threads of one
+// workgroup.
+template <int L, int NT>
+__device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                               int32_t* piv, int32_t* info)
 {
-    __shared__ uint32_t sv[L + 2][PIV_THREADS];
-    __shared__ int32_t sidx[PIV_THREADS];
+    __shared__ uint32_t sv[L + 2][NT];
+    __shared__ int32_t sidx[NT];
     const int tid = threadIdx.x;
     int32_t best = -1;
     MP<L> bv = mp_zero<L>();
-    for (int64_t i = c + tid; i < n; i += PIV_THREADS) {
+    for (int64_t i = c + tid; i < n; i += NT) {
         const MP<L> v = ldm<L>(bs, a, i, c);
         if (best < 0 || cmp_abs<L>(v, bv) > 0) {
             best = (int32_t)i;
@@ -51,7 +52,7 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
     sv[L + 1][tid] = bv.s;
     sidx[tid] = best;
     __syncthreads();
-    for (int s = PIV_THREADS / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (tid < s) {
             const int32_t i1 = sidx[tid], i2 = sidx[tid + s];
             bool take = false;
@@ -89,7 +90,7 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
     if (r != c) {
         uint32_t* p = base_ptr(bs, a.base) + a.off;
         const int64_t w = je - j0;
-        for (int64_t e = tid; e < w * (L + 2); e += PIV_THREADS) {
+        for (int64_t e = tid; e < w * (L + 2); e += NT) {
             const int64_t j = j0 + e % w, q = e / w;
             uint32_t* x = p + q * a.ps + c * a.ld + j;
             uint32_t* y = p + q * a.ps + r * a.ld + j;
@@ -98,6 +99,13 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
             *y = t;
         }
     }
+}
+
+template <int L>
+__global__ void __launch_bounds__(PIV_THREADS)
+k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info)
+{
+    pivot_and_swap<L, PIV_THREADS>(bs, a, n, c, j0, je, piv, info);
 }
 
 // one workgroup per row i in (c, n): l = a_ic / a_cc by one lane, shared in
@@ -129,12 +137,39 @@ k_lu_eliminate(Bases bs, MatRef a, int64_t c, int64_t je)
 }
 
 // U12 := L11^-1 A12: one workgroup per column j >= je, one lane per panel row;
-// step t updates rows r > t with row t, which step t-1 finished
+// step t updates rows r > t with row t, which step t-1 finished.  For panels
+// of up to 64 rows the column stays in registers (lane r holds row r; the
+// finished row t is broadcast through LDS); wider panels go through memory.
 template <int L>
 __global__ void __launch_bounds__(64)
 k_lu_u12(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
 {
     const int64_t j = je + blockIdx.x;
+    if (kb <= 64) {
+        __shared__ uint32_t su[L + 2];
+        const int r = threadIdx.x;
+        MP<L> x = r < kb ? ldm<L>(bs, a, j0 + r, j) : mp_zero<L>();
+        for (int64_t t = 0; t < kb - 1; t++) {
+            if (r == t) {
+#pragma unroll
+                for (int q = 0; q < L; q++) su[q] = x.m[q];
+                su[L] = (uint32_t)x.e;
+                su[L + 1] = x.s;
+            }
+            __syncthreads();
+            if (r > t && r < kb) {
+                MP<L> u;
+#pragma unroll
+                for (int q = 0; q < L; q++) u.m[q] = su[q];
+                u.e = (int32_t)su[L];
+                u.s = su[L + 1];
+                x = sub_rn<L>(x, mul_rn<L>(ldm<L>(bs, a, j0 + r, j0 + t), u));
+            }
+            __syncthreads();
+        }
+        if (r < kb) stm<L>(bs, a, j0 + r, j, x);
+        return;
+    }
     for (int64_t t = 0; t < kb - 1; t++) {
         const MP<L> u = ldm<L>(bs, a, j0 + t, j);
         for (int64_t r = t + 1 + threadIdx.x; r < kb; r += 64)
