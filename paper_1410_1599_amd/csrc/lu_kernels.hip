@@ -288,6 +288,122 @@ unsigned blocks_for(int64_t n, int per)
 
 }  // namespace
 
+// The same solve with the vector in registers: thread t owns rows t + k * 512
+// (k < RPT, n <= 512 RPT; 512 threads leave 256 registers per lane).  The row swaps are first composed into one
+// permutation in LDS; at every step the owner of the finished entry publishes
+// it through LDS (two alternating slots, one barrier per step) and every
+// other row applies its update in the same order as above.
+constexpr int SOLVE_REG_THREADS = 512;
+
+template <int L, int RPT>
+__global__ void __launch_bounds__(SOLVE_REG_THREADS)
+k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
+{
+    __shared__ int32_t perm[SOLVE_REG_THREADS * RPT];
+    __shared__ uint32_t sx[2][L + 2];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int r = tid + k * SOLVE_REG_THREADS;
+        if (r < n) perm[r] = r;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int t = 0; t < (int)n; t++) {
+            const int p = piv[t];
+            const int w = perm[t];
+            perm[t] = perm[p];
+            perm[p] = w;
+        }
+    }
+    __syncthreads();
+    MP<L> v[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int r = tid + k * SOLVE_REG_THREADS;
+        v[k] = r < n ? ldm<L>(bs, x, perm[r], 0) : mp_zero<L>();
+    }
+    auto publish = [&](int t, const MP<L>& y) {
+        uint32_t* d = sx[t & 1];
+#pragma unroll
+        for (int q = 0; q < L; q++) d[q] = y.m[q];
+        d[L] = (uint32_t)y.e;
+        d[L + 1] = y.s;
+    };
+    auto fetch = [&](int t) {
+        const uint32_t* d = sx[t & 1];
+        MP<L> y;
+#pragma unroll
+        for (int q = 0; q < L; q++) y.m[q] = d[q];
+        y.e = (int32_t)d[L];
+        y.s = d[L + 1];
+        return y;
+    };
+    // the factor entries of step t + 1 are loaded while step t computes
+    MP<L> fc[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int r = tid + k * SOLVE_REG_THREADS;
+        fc[k] = (r > 0 && r < n) ? ldm<L>(bs, lu, r, 0) : mp_zero<L>();
+    }
+    for (int t = 0; t < (int)n; t++) {              // L y = P b, unit diagonal
+        if (tid == t % SOLVE_REG_THREADS) {
+#pragma unroll
+            for (int k = 0; k < RPT; k++)
+                if (k == t / SOLVE_REG_THREADS) publish(t, v[k]);
+        }
+        __syncthreads();
+        const MP<L> yt = fetch(t);
+        MP<L> fn[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+            const int r = tid + k * SOLVE_REG_THREADS;
+            fn[k] = (r > t + 1 && r < n) ? ldm<L>(bs, lu, r, t + 1) : mp_zero<L>();
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+            const int r = tid + k * SOLVE_REG_THREADS;
+            if (r > t && r < n) v[k] = sub_rn<L>(v[k], mul_rn<L>(fc[k], yt));
+            fc[k] = fn[k];
+        }
+    }
+    // column n - 1 of U (its diagonal entry for the owner of row n - 1)
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int r = tid + k * SOLVE_REG_THREADS;
+        fc[k] = r < n ? ldm<L>(bs, lu, r, n - 1) : mp_zero<L>();
+    }
+    for (int t = (int)n - 1; t >= 0; t--) {         // U x = y
+        if (tid == t % SOLVE_REG_THREADS) {
+#pragma unroll
+            for (int k = 0; k < RPT; k++)
+                if (k == t / SOLVE_REG_THREADS) {
+                    v[k] = div_rn<L>(v[k], fc[k]);
+                    publish(t, v[k]);
+                }
+        }
+        __syncthreads();
+        const MP<L> xt = fetch(t);
+        MP<L> fn[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+            const int r = tid + k * SOLVE_REG_THREADS;
+            fn[k] = (t >= 1 && r <= t - 1) ? ldm<L>(bs, lu, r, t - 1) : mp_zero<L>();
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+            const int r = tid + k * SOLVE_REG_THREADS;
+            if (r < t) v[k] = sub_rn<L>(v[k], mul_rn<L>(fc[k], xt));
+            fc[k] = fn[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int r = tid + k * SOLVE_REG_THREADS;
+        if (r < n) stm<L>(bs, x, r, 0, v[k]);
+    }
+}
+
 #define MPG_DISPATCH_L(L_, CALL)           \
     switch (L_) {                          \
     case 4: { constexpr int LL = 4; CALL; break; }   \
@@ -338,7 +454,18 @@ hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const in
                            hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve<LL>), dim3(1), dim3(SOLVE_THREADS), 0, s, bs, lu, x, piv, n));
+    const dim3 g(1), b(SOLVE_REG_THREADS);
+    if (n <= SOLVE_REG_THREADS) {
+        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 1>), g, b, 0, s, bs, lu, x, piv, n));
+    } else if (n <= 2 * SOLVE_REG_THREADS) {
+        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 2>), g, b, 0, s, bs, lu, x, piv, n));
+    } else if (n <= 4 * SOLVE_REG_THREADS) {
+        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 4>), g, b, 0, s, bs, lu, x, piv, n));
+    } else if (n <= 8 * SOLVE_REG_THREADS) {
+        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 8>), g, b, 0, s, bs, lu, x, piv, n));
+    } else {
+        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve<LL>), dim3(1), dim3(SOLVE_THREADS), 0, s, bs, lu, x, piv, n));
+    }
     return hipGetLastError();
 }
 
