@@ -540,8 +540,10 @@ int ref_scalar(int op, int p, const uint32_t *x, const uint32_t *y, uint32_t *r)
     return store(mc, r, 1, 1, L);
 }
 
-/* Section 4 blocked LU, with partial pivoting; see oracle/lu.py for the readings */
-static int lu(mat a, int32_t *piv, int64_t panel, int algo, int64_t cutoff, int policy, int L)
+/* Section 4 blocked LU, with partial pivoting (pivot != 0) or, as in the
+   paper, without (pivot == 0: every pivot is the diagonal entry); see
+   oracle/lu.py for the readings */
+static int lu(mat a, int32_t *piv, int64_t panel, int algo, int64_t cutoff, int policy, int pivot, int L)
 {
     int64_t n = a.rows;
     int info = 0;
@@ -549,7 +551,7 @@ static int lu(mat a, int32_t *piv, int64_t panel, int algo, int64_t cutoff, int 
         int64_t kb = panel < n - j0 ? panel : n - j0, je = j0 + kb;
         for (int64_t c = j0; c < je; c++) {
             int64_t r = c;
-            for (int64_t i = c + 1; i < n; i++)
+            for (int64_t i = c + 1; pivot && i < n; i++)
                 if (mp_cmpabs(&AT(a, i, c), &AT(a, r, c), L) > 0) r = i;
             piv[c] = (int32_t)r;
             if (r != c)
@@ -589,17 +591,23 @@ static int lu(mat a, int32_t *piv, int64_t panel, int algo, int64_t cutoff, int 
     return info;
 }
 
-int ref_lu(int64_t n, int p, int64_t panel, int algo, int64_t cutoff, int policy,
-           uint32_t *A, int64_t lda, int64_t psa, int32_t *piv, int32_t *info)
+int ref_lu_ex(int64_t n, int p, int64_t panel, int algo, int64_t cutoff, int policy, int pivot,
+              uint32_t *A, int64_t lda, int64_t psa, int32_t *piv, int32_t *info)
 {
     if (p % 32 || p <= 0 || p / 32 > MAXL) return -2;
     int L = p / 32;
     mat a = mat_new(n, n);
     load(a, A, lda, psa, L);
-    *info = lu(a, piv, panel, algo, cutoff, policy, L);
+    *info = lu(a, piv, panel, algo, cutoff, policy, pivot, L);
     int rc = store(a, A, lda, psa, L);
     mat_free(a);
     return rc;
+}
+
+int ref_lu(int64_t n, int p, int64_t panel, int algo, int64_t cutoff, int policy,
+           uint32_t *A, int64_t lda, int64_t psa, int32_t *piv, int32_t *info)
+{
+    return ref_lu_ex(n, p, panel, algo, cutoff, policy, 1, A, lda, psa, piv, info);
 }
 
 /* x := solve with the factors (swaps, unit-lower forward, upper backward) */

@@ -30,6 +30,8 @@ def lib():
         L.ref_scalar.restype = i32
         L.ref_lu.argtypes = [i64, i32, i64, i32, i64, i32, u32p, i64, i64, i32p, i32p]
         L.ref_lu.restype = i32
+        L.ref_lu_ex.argtypes = [i64, i32, i64, i32, i64, i32, i32, u32p, i64, i64, i32p, i32p]
+        L.ref_lu_ex.restype = i32
         L.ref_lu_solve.argtypes = [i64, i32, u32p, i64, i64, i32p, u32p, i64]
         L.ref_lu_solve.restype = i32
         L.ref_lu_residual.argtypes = [i64, i32, u32p, i64, i64, u32p, i64, i64, i32p,
@@ -77,15 +79,16 @@ def scalar(op, p, x, y):
     return r
 
 
-def lu(A, p, panel=64, algo="winograd", cutoff=32, policy="peel"):
-    """Returns (LU planes, piv, info); A is not modified."""
+def lu(A, p, panel=64, algo="winograd", cutoff=32, policy="peel", pivot=True):
+    """Returns (LU planes, piv, info); A is not modified.  pivot=False: the
+    paper's LU without row exchanges (piv is then the identity)."""
     n = A.shape[1]
     F = np.ascontiguousarray(A.copy())
     piv = np.zeros(n, dtype=np.int32)
     info = ctypes.c_int32(0)
-    rc = lib().ref_lu(n, p, panel, ALGO[algo], cutoff, POLICY[policy], _p(F), F.shape[2],
-                      F.shape[1] * F.shape[2], piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                      ctypes.byref(info))
+    rc = lib().ref_lu_ex(n, p, panel, ALGO[algo], cutoff, POLICY[policy], 1 if pivot else 0, _p(F), F.shape[2],
+                         F.shape[1] * F.shape[2], piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         ctypes.byref(info))
     if rc:
         raise RuntimeError("ref_lu failed: %d" % rc)
     return F, piv, info.value

@@ -23,8 +23,12 @@ from . import mpnum
 from . import gemm as G
 
 
-def lu(A, p, panel=64, algo=G.WINOGRAD, cutoff=32, policy=G.PEEL):
-    """Factor a copy of A in place.  Returns (LU, piv, info)."""
+def lu(A, p, panel=64, algo=G.WINOGRAD, cutoff=32, policy=G.PEEL, pivot=True):
+    """Factor a copy of A in place.  Returns (LU, piv, info).
+
+    pivot=False is the paper's LU as published (Section 4): no row
+    exchanges, every pivot the diagonal entry, piv the identity; a zero
+    diagonal entry sets info and skips that column like a zero pivot."""
     n = len(A)
     a = [list(r) for r in A]
     piv = list(range(n))
@@ -36,7 +40,7 @@ def lu(A, p, panel=64, algo=G.WINOGRAD, cutoff=32, policy=G.PEEL):
         # 1. panel: unblocked right-looking elimination on columns j0..je-1
         for c in range(j0, je):
             r = c
-            for i in range(c + 1, n):
+            for i in range(c + 1, n if pivot else c + 1):
                 if mpnum.cmp_abs(a[i][c], a[r][c]) > 0:
                     r = i
             piv[c] = r

@@ -229,6 +229,25 @@ def hilbert(n, p, ld=None):
     return out
 
 
+def lotkin(n, p, ld=None):
+    """The Lotkin matrix: the first row all ones, a_ij = the p-bit value
+    nearest 1 / (i + j - 1) below it (1-based i, j)."""
+    out = hilbert(n, p, ld)
+    for j in range(n):
+        set_entry(out, 0, j, (1 << (p - 1), 1), p)
+    return out
+
+
+def arange_column(n, p):
+    """The n x 1 column x = [0, 1, ..., n - 1] (exact p-bit integers)."""
+    out = empty(n, 1, p)
+    for i in range(n):
+        if i:
+            e = i.bit_length()
+            set_entry(out, i, 0, (i << (p - e), e), p)
+    return out
+
+
 def _recip_value(q, p):
     """(sig, e) of the nearest p-bit value to 1/q, by integer division only."""
     # 1/q lies in [2**(e-1), 2**e) with e = -(bitlen(q-1)) for q >= 2, e = 1 for q = 1

@@ -159,3 +159,62 @@ def test_c_residual_matches_exact():
     ex = LU.residual_exact(Ao, I.from_planes(F, p), list(piv), p)
     assert ex > 0
     assert abs(l2 - math.log2(ex)) < 1e-6
+
+
+@pytest.mark.parametrize("algo,panel,cutoff", [("winograd", 4, 1), ("strassen", 5, 1), ("simple", 13, 8)])
+def test_unpivoted_exact_factorisation_recovered(algo, panel, cutoff):
+    """The paper's LU without row exchanges (Section 4) on A = L U with small
+    dyadic factors whose multipliers are not the largest in their columns
+    (|l_ij| up to 4): nothing rounds, so the factors come back exactly, the
+    pivots are the identity, and partial pivoting would have swapped."""
+    p = 128
+    n = 11
+    rng = random.Random(9)
+    L = [[Fraction(0)] * n for _ in range(n)]
+    U = [[Fraction(0)] * n for _ in range(n)]
+    for i in range(n):
+        L[i][i] = Fraction(1)
+        for j in range(i):
+            L[i][j] = Fraction(rng.randrange(-63, 64), 16)
+        U[i][i] = Fraction(rng.choice((1, -1)) * rng.randrange(1, 8), 8)
+        for j in range(i + 1, n):
+            U[i][j] = Fraction(rng.randrange(-31, 32), 8)
+    A = [[sum(L[i][k] * U[k][j] for k in range(n)) for j in range(n)] for i in range(n)]
+    Am = to_mp(A, p)
+    F, piv, info = LU.lu(Am, p, panel=panel, algo=algo, cutoff=cutoff, pivot=False)
+    assert info == 0 and piv == list(range(n))
+    for i in range(n):
+        for j in range(n):
+            v = mpnum.to_fraction(F[i][j], p)
+            assert v == (L[i][j] if j < i else U[i][j]), (i, j)
+    _, pivp, _ = LU.lu(Am, p, panel=panel, algo=algo, cutoff=cutoff)
+    assert pivp != list(range(n))
+
+
+@pytest.mark.parametrize("p", [128, 512])
+@pytest.mark.parametrize("kind", ["random", "lotkin"])
+def test_c_oracle_unpivoted_lu_matches_python(p, kind):
+    n = 17
+    A = I.uniform_pm1(n, n, p, 8) if kind == "random" else I.lotkin(n, p)
+    Ao = I.from_planes(A, p)
+    for algo, panel, cut in (("winograd", 8, 2), ("simple", 5, 4)):
+        Fp, pivp, infop = LU.lu(Ao, p, panel=panel, algo=algo, cutoff=cut, pivot=False)
+        Fc, pivc, infoc = cref.lu(A, p, panel=panel, algo=algo, cutoff=cut, pivot=False)
+        assert list(pivc) == pivp == list(range(n)) and infoc == infop == 0
+        assert I.from_planes(Fc, p) == Fp, (algo, panel)
+
+
+def test_unpivoted_lotkin_solve_close_to_arange():
+    """x = [0, 1, ..., n-1] and b = A x for the Lotkin matrix (the paper's
+    ill-conditioned case, Section 4): the unpivoted factors solve it to within
+    the condition number (about 1e8 at n = 8) times the unit roundoff."""
+    p, n = 256, 8
+    A = I.lotkin(n, p)
+    Ao = I.from_planes(A, p)
+    x = I.from_planes(I.arange_column(n, p), p)
+    b = [r[0] for r in G.gemm(Ao, x, p, algo=G.SIMPLE)]
+    F, piv, info = LU.lu(Ao, p, panel=3, algo=G.WINOGRAD, cutoff=1, pivot=False)
+    assert info == 0
+    xs = LU.solve(F, piv, b, p)
+    err = max(abs(mpnum.to_fraction(v, p) - i) for i, v in enumerate(xs))
+    assert err < Fraction(1, 2 ** 200)
