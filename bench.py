@@ -73,6 +73,10 @@ def parse():
     ap.add_argument("--slice-steps", type=int, default=3, help="timed steps of the INT8-slice path (0: skip)")
     ap.add_argument("--lu", type=int, default=1, help="run the LU workload (n=512, 512 bits, panel 64, Winograd "
                                                      "cutoff 32, random and Hilbert inputs); 0: skip")
+    ap.add_argument("--lu-paper", type=int, default=1,
+                    help="the paper's LU experiment (Section 4): no pivoting, n=1024, panel K = 32..320 with Winograd "
+                         "trailing updates (cutoff 32) against column-wise LU (one panel), random at 256 bits and "
+                         "Lotkin at 512 bits, x = [0..n-1]; 0: skip")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving run (0: skip): Poisson arrivals at 0.8 x the measured "
                          "saturated rate, 90%% products / 10%% LU solves, 128/256/512 bits")
@@ -265,6 +269,42 @@ def main():
         lu_res["config"] = ("n=512 prec=512 panel=64 winograd cutoff=32, b = A*ones; factors and pivots are checked "
                             "bit for bit against the CPU oracle by the GPU tests")
 
+    lu_paper = None
+    if args.lu_paper:
+        lu_paper = {"config": "n=1024, no pivoting, Winograd trailing updates with cutoff 32; b = A x with "
+                              "x = [0..n-1] by Simple; times are the second of two runs per panel width"}
+        npl = 1024
+        for kind, pl in (("random", 256), ("lotkin", 512)):
+            Ah = I.uniform_pm1(npl, npl, pl, 5) if kind == "random" else I.lotkin(npl, pl)
+            dAl = mp.to_device(Ah)
+            xt = mp.to_device(I.arange_column(npl, pl))
+            db = mp.empty(npl, 1, pl)
+            mp.mp_gemm(npl, npl, 1, pl, mp.SIMPLE, 0, dAl, xt, db)
+            work = dAl.clone()
+            piv = torch.zeros(npl, dtype=torch.int32, device="cuda")
+            times = {}
+            for K in [32 * a for a in range(1, 11)] + [npl]:
+                for _ in range(2):
+                    work.copy_(dAl)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    info = mp.mp_lu_nopivot(npl, pl, work, piv, K, mp.WINOGRAD, 32)
+                    torch.cuda.synchronize()
+                    tk = time.perf_counter() - t0
+                times["column-wise" if K == npl else "K=%d" % K] = round(tk * 1e3, 2)
+            bestK = min((k for k in times if k != "column-wise"), key=lambda k: times[k])
+            work.copy_(dAl)
+            info = mp.mp_lu_nopivot(npl, pl, work, piv, int(bestK[2:]), mp.WINOGRAD, 32)
+            dx = db.clone()
+            mp.mp_lu_solve(npl, pl, work, piv, dx)
+            xh = mp.to_host(dx)
+            err = max(abs(Fraction(sig) * Fraction(2) ** (e - pl) - i)
+                      for i, (sig, e) in enumerate(I.entry(xh, i, 0, pl) for i in range(npl)))
+            lu_paper[kind] = {"prec": pl, "info": info, "lu_ms": times, "best": bestK,
+                              "time_saved_vs_columnwise": round(1 - times[bestK] / times["column-wise"], 4),
+                              "max_abs_x_minus_xtrue": float(err)}
+            del dAl, work, db, dx
+
     serve_res = None
     if args.serve_requests > 0:
         del dA, dB, dC
@@ -310,7 +350,7 @@ def main():
                                "seeds 6/7" % (n, p, args.algo, args.cutoff),
                    "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others, "slice": slice_res,
-        "accuracy": accuracy, "serve": serve_res, "lu": lu_res,
+        "accuracy": accuracy, "serve": serve_res, "lu": lu_res, "lu_paper": lu_paper,
     }
     print(json.dumps(out))
 

@@ -215,6 +215,18 @@ int mp_lu_async(int64_t n, int prec, uint32_t *A, int64_t lda, int64_t psa, int3
                 int panel, int algo, int cutoff, int policy);
 
 /*
+ * The LU of the paper as published (Section 4): the same blocked algorithm
+ * without row exchanges, every pivot the diagonal entry a_cc.  piv (device, n
+ * int32) receives the identity, so mp_lu_solve applies to the factors
+ * unchanged.  *info (host) is 0, or c + 1 for the first column whose diagonal
+ * entry became exactly zero; that column is skipped (no quotients, no update)
+ * and the factorisation completes.  Arguments and errors as mp_lu_ex.
+ * Synchronises the stream to read info.
+ */
+int mp_lu_nopivot(int64_t n, int prec, uint32_t *A, int64_t lda, int64_t psa, int32_t *piv, int32_t *info,
+                  int panel, int algo, int cutoff, int policy);
+
+/*
  * Solve A x = b from the factors of mp_lu: the row swaps of piv in order,
  * forward substitution with the unit lower factor, back substitution with the
  * upper factor (true quotients by the diagonal).  b (n x 1, plane stride psb)

@@ -31,8 +31,9 @@ hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ld, int64_t ps, int64
 hipError_t launch_fill_i32(int32_t* X, int64_t count, int32_t value, hipStream_t s);
 
 // LU building blocks (lu_kernels.hip); the matrix is one MatRef on base A
+// search == 0: no row exchange, the pivot is a_cc
 hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
-                                int32_t* piv, int32_t* info, hipStream_t s);
+                                int32_t* piv, int32_t* info, int search, hipStream_t s);
 hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, hipStream_t s);
 hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t kb, int64_t je, int64_t n,
                          hipStream_t s);

@@ -1,5 +1,6 @@
-// lu.cpp -- host driver of the blocked LU with partial pivoting (Section 4)
-// and of the solve; the C-ABI functions mp_lu, mp_lu_ex and mp_lu_solve.
+// lu.cpp -- host driver of the blocked LU with partial pivoting (Section 4),
+// of the paper's unpivoted LU and of the solve; the C-ABI functions mp_lu,
+// mp_lu_ex, mp_lu_async, mp_lu_nopivot and mp_lu_solve.
 //
 // For each panel of K columns starting at j0 (the last one may be narrower):
 //   per column c: pivot search, row swap inside the panel, multipliers
@@ -30,8 +31,9 @@ namespace {
 
 // info_dev: device int32 that receives info (the first zero pivot + 1, or 0);
 // with info_host non-NULL the stream is synchronised and info copied there
+// pivot == 0: the paper's LU as published (no row exchanges; piv = identity)
 int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info_host,
-           int32_t* info_dev, int panel, int algo, int cutoff, int policy, hipStream_t s)
+           int32_t* info_dev, int panel, int algo, int cutoff, int policy, hipStream_t s, int pivot)
 {
     int rc = MP_OK;
     const int64_t m2max = n > panel ? n - panel : 0;
@@ -51,10 +53,10 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
             // pivot search and the swap inside the panel; then multipliers and
             // the panel's rank-one update (a zero pivot leaves a zero column, whose
             // quotients and updates are exact no-ops)
-            MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, s));
+            MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, pivot, s));
             MPG_TRY(launch_lu_eliminate(L, bs, a, n, c, je, s));
         }
-        MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, je, n, s));
+        if (pivot) MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, je, n, s));
         if (je >= n) break;
         MPG_TRY(launch_lu_u12(L, bs, a, j0, kb, je, n, s));
         const int64_t m2 = n - je;
@@ -101,7 +103,7 @@ int mp_lu_ex(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int32_t
     if ((rc = lu_check(n, prec, A, lda, psa, piv, panel, algo, cutoff, policy, &L))) return rc;
     if (n == 0) return MP_OK;
     if ((rc = device_check())) return rc;
-    if ((rc = lu_run(n, L, A, lda, psa, piv, info, nullptr, panel, algo, cutoff, policy, g_stream))) return rc;
+    if ((rc = lu_run(n, L, A, lda, psa, piv, info, nullptr, panel, algo, cutoff, policy, g_stream, 1))) return rc;
     return device_check();
 }
 
@@ -113,7 +115,20 @@ int mp_lu_async(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int3
     if ((rc = lu_check(n, prec, A, lda, psa, piv, panel, algo, cutoff, policy, &L))) return rc;
     if (n == 0) return launch_fill_i32(info_dev, 1, 0, g_stream) == hipSuccess ? MP_OK : MP_E_DEVICE;
     if ((rc = device_check())) return rc;
-    if ((rc = lu_run(n, L, A, lda, psa, piv, nullptr, info_dev, panel, algo, cutoff, policy, g_stream))) return rc;
+    if ((rc = lu_run(n, L, A, lda, psa, piv, nullptr, info_dev, panel, algo, cutoff, policy, g_stream, 1))) return rc;
+    return device_check();
+}
+
+int mp_lu_nopivot(int64_t n, int prec, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv, int32_t* info, int panel,
+                  int algo, int cutoff, int policy)
+{
+    int L, rc;
+    if (!info) return set_err(MP_E_ARG, "info is NULL");
+    *info = 0;
+    if ((rc = lu_check(n, prec, A, lda, psa, piv, panel, algo, cutoff, policy, &L))) return rc;
+    if (n == 0) return MP_OK;
+    if ((rc = device_check())) return rc;
+    if ((rc = lu_run(n, L, A, lda, psa, piv, info, nullptr, panel, algo, cutoff, policy, g_stream, 0))) return rc;
     return device_check();
 }
 

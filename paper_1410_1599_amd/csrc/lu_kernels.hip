@@ -101,15 +101,23 @@ __device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int6
     }
 }
 
+// search == 0: the paper's LU without row exchanges: the pivot is a_cc
 template <int L>
 __global__ void __launch_bounds__(PIV_THREADS)
-k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info)
+k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info,
+                int search)
 {
-    pivot_and_swap<L, PIV_THREADS>(bs, a, n, c, j0, je, piv, info);
+    if (search) {
+        pivot_and_swap<L, PIV_THREADS>(bs, a, n, c, j0, je, piv, info);
+    } else if (threadIdx.x == 0) {
+        piv[c] = (int32_t)c;
+        if (is_zero<L>(ldm<L>(bs, a, c, c)) && info[0] == 0) info[0] = (int32_t)(c + 1);
+    }
 }
 
 // one workgroup per row i in (c, n): l = a_ic / a_cc by one lane, shared in
-// LDS, then a_ij := a_ij - l a_cj for the panel columns j in (c, je)
+// LDS, then a_ij := a_ij - l a_cj for the panel columns j in (c, je); a zero
+// pivot skips the column (no quotient, no update)
 constexpr int ELIM_THREADS = 64;
 
 template <int L>
@@ -117,16 +125,22 @@ __global__ void __launch_bounds__(ELIM_THREADS)
 k_lu_eliminate(Bases bs, MatRef a, int64_t c, int64_t je)
 {
     __shared__ uint32_t sl[L + 2];
+    __shared__ int32_t skip;
     const int64_t i = c + 1 + blockIdx.x;
     if (threadIdx.x == 0) {
-        const MP<L> l = div_rn<L>(ldm<L>(bs, a, i, c), ldm<L>(bs, a, c, c));
-        stm<L>(bs, a, i, c, l);
+        const MP<L> d = ldm<L>(bs, a, c, c);
+        skip = is_zero<L>(d);
+        if (!skip) {
+            const MP<L> l = div_rn<L>(ldm<L>(bs, a, i, c), d);
+            stm<L>(bs, a, i, c, l);
 #pragma unroll
-        for (int q = 0; q < L; q++) sl[q] = l.m[q];
-        sl[L] = (uint32_t)l.e;
-        sl[L + 1] = l.s;
+            for (int q = 0; q < L; q++) sl[q] = l.m[q];
+            sl[L] = (uint32_t)l.e;
+            sl[L + 1] = l.s;
+        }
     }
     __syncthreads();
+    if (skip) return;
     MP<L> l;
 #pragma unroll
     for (int q = 0; q < L; q++) l.m[q] = sl[q];
@@ -413,10 +427,10 @@ k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
     }
 
 hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
-                                int32_t* piv, int32_t* info, hipStream_t s)
+                                int32_t* piv, int32_t* info, int search, hipStream_t s)
 {
     MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_pivot_swap<LL>), dim3(1), dim3(PIV_THREADS), 0, s, bs, a, n, c, j0, je,
-                                         piv, info));
+                                         piv, info, search));
     return hipGetLastError();
 }
 

@@ -219,13 +219,15 @@ def integers(rows, cols, p, seed, bits=10):
 def hilbert(n, p, ld=None):
     """a_ij = the p-bit value nearest 1 / (i + j - 1) (1-based i, j)."""
     out = empty(n, n, p, ld)
-    cache = {}
-    for i in range(n):
-        for j in range(n):
-            q = i + j + 1
-            if q not in cache:
-                cache[q] = _recip_value(q, p)
-            set_entry(out, i, j, cache[q], p)
+    if n == 0:
+        return out
+    # the 2n - 1 distinct values 1/q, q = 1 .. 2n - 1, as plane columns, then
+    # gathered by q = i + j + 1
+    V = empty(1, 2 * n, p)
+    for q in range(1, 2 * n):
+        set_entry(V, 0, q, _recip_value(q, p), p)
+    idx = np.add.outer(np.arange(n), np.arange(n)) + 1
+    out[:, :, :n] = V[:, 0, :][:, idx]
     return out
 
 

@@ -56,6 +56,7 @@ def _load():
         "mp_plan_info": ([i64, i64, i64, i32, i32, i32, i32, i32p, dp, dp, i64p, i64p], i32),
         "mp_lu": ([i64, i32, vp, i64, i64, vp, i32p], i32),
         "mp_lu_ex": ([i64, i32, vp, i64, i64, vp, i32p, i32, i32, i32, i32], i32),
+        "mp_lu_nopivot": ([i64, i32, vp, i64, i64, vp, i32p, i32, i32, i32, i32], i32),
         "mp_lu_solve": ([i64, i32, vp, i64, i64, vp, vp, i64], i32),
         "mp_release_workspace": ([], i32),
         "mp_profile": ([i32], i32),
@@ -191,6 +192,16 @@ def mp_lu_ex(n, prec, A, piv, panel=64, algo=WINOGRAD, cutoff=32, policy=PEEL):
     pa, lda, psa = _mat(A)
     _check(lib.mp_lu_ex(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()), ctypes.byref(info),
                         int(panel), int(algo), int(cutoff), int(policy)))
+    return info.value
+
+
+def mp_lu_nopivot(n, prec, A, piv, panel=64, algo=WINOGRAD, cutoff=32, policy=PEEL):
+    """The paper's LU without row exchanges; piv receives the identity."""
+    mp_set_stream()
+    info = ctypes.c_int(0)
+    pa, lda, psa = _mat(A)
+    _check(lib.mp_lu_nopivot(n, prec, pa, lda, psa, ctypes.c_void_p(piv.data_ptr()), ctypes.byref(info),
+                             int(panel), int(algo), int(cutoff), int(policy)))
     return info.value
 
 

@@ -81,3 +81,55 @@ def test_lu_n512_p512_panel64_winograd(kind):
     l2, val = cref.lu_residual(A, Fg, pg, p)
     print("%s: residual %.3g (2^%.1f)" % (kind, val, l2))
     assert l2 < -p + 20
+
+
+def gpu_lu_nopivot(A, p, panel, algo, cutoff, policy=mp.PEEL):
+    n = A.shape[1]
+    dA = mp.to_device(A)
+    piv = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    info = mp.mp_lu_nopivot(n, p, dA, piv, panel, algo, cutoff, policy)
+    torch.cuda.synchronize()
+    return mp.to_host(dA), piv.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("kind", ["random", "lotkin"])
+def test_lu_nopivot_small_against_oracle(p, kind):
+    """The paper's LU without row exchanges (Section 4)."""
+    n = 45
+    A = I.uniform_pm1(n, n, p, 21) if kind == "random" else I.lotkin(n, p)
+    for panel, algo, cut in ((8, mp.WINOGRAD, 2), (7, mp.STRASSEN, 1), (45, mp.SIMPLE, 1)):
+        names = {mp.WINOGRAD: "winograd", mp.STRASSEN: "strassen", mp.SIMPLE: "simple"}
+        Fc, pc, ic = cref.lu(A, p, panel=panel, algo=names[algo], cutoff=cut, pivot=False)
+        Fg, pg, ig = gpu_lu_nopivot(A, p, panel, algo, cut)
+        assert ig == ic == 0
+        assert list(pg) == list(range(n))
+        assert planes_equal(Fg, Fc), (panel, first_mismatch(Fg, Fc, p))
+
+
+def test_lu_nopivot_zero_diagonal_skips_column():
+    p, n = 256, 9
+    A = I.uniform_pm1(n, n, p, 4)
+    A[:, 0, 0] = 0                                   # a_00 = +0 (all planes zero)
+    Fc, pc, ic = cref.lu(A, p, panel=4, algo="winograd", cutoff=1, pivot=False)
+    Fg, pg, ig = gpu_lu_nopivot(A, p, 4, mp.WINOGRAD, 1)
+    assert ig == ic == 1
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+
+
+def test_lu_nopivot_n512_lotkin_and_solve():
+    """The paper's ill-conditioned case: the Lotkin matrix, x = [0..n-1],
+    b = A x (Simple, one rounding per operation), unpivoted LU with Winograd
+    trailing updates, then the solve; factors and solution bit-exact to the
+    oracle."""
+    p, n = 512, 512
+    A = I.lotkin(n, p)
+    Fc, pc, ic = cref.lu(A, p, panel=64, algo="winograd", cutoff=32, pivot=False)
+    Fg, pg, ig = gpu_lu_nopivot(A, p, 64, mp.WINOGRAD, 32)
+    assert ig == ic == 0
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+    b = cref.gemm(A, I.arange_column(n, p), p, algo="simple")
+    xg = gpu_solve(Fg, pg, b, p)
+    assert planes_equal(xg, cref.lu_solve(Fc, pc, b, p))
+    err = max(abs(mpnum.to_fraction(I.entry(xg, i, 0, p), p) - i) for i in range(n))
+    print("Lotkin n=512, 512 bits, unpivoted: max |x - x_true| = %.3g" % float(err))
