@@ -77,6 +77,10 @@ def parse():
                     help="the paper's LU experiment (Section 4): no pivoting, n=1024, panel K = 32..320 with Winograd "
                          "trailing updates (cutoff 32) against column-wise LU (one panel), random at 256 bits and "
                          "Lotkin at 512 bits, x = [0..n-1]; 0: skip")
+    ap.add_argument("--paper-grid", type=int, default=1,
+                    help="the paper's own matrices (Section 3: a_ij = sqrt5 (i+j-1), b_ij = sqrt3 (n-i+1)) at 128 bits, "
+                         "cutoff 32, mixed odd-size policy: square n = 255..2049 and Table 5's m = n = 1024 with l = "
+                         "63..513; times and sampled relative errors against the closed form; 0: skip")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving run (0: skip): Poisson arrivals at 0.8 x the measured "
                          "saturated rate, 90%% products / 10%% LU solves, 128/256/512 bits")
@@ -305,6 +309,47 @@ def main():
                               "max_abs_x_minus_xtrue": float(err)}
             del dAl, work, db, dx
 
+    paper_grid = None
+    if args.paper_grid:
+        from math import isqrt
+        pg = 128
+
+        def rel_err(C, m, l, n):
+            # rows 0, m/2, m-1, every column; exact c_ij = sqrt15 R_i, sqrt15 R_i to 3p fraction bits
+            tail = sum(k * (n - k + 1) for k in range(1, l + 1))
+            worst = 0.0
+            for i in sorted({0, m // 2, m - 1}):
+                R = i * l * (2 * n - l + 1) // 2 + tail
+                K = 3 * pg
+                X = Fraction(isqrt(15 * R * R << (2 * K)), 1 << K)
+                for j in range(n):
+                    sig, e = I.entry(C, i, j, pg)
+                    worst = max(worst, float(abs(Fraction(sig) * Fraction(2) ** (e - pg) - X) / X))
+            return worst
+
+        def run(m, l, n, algos):
+            A8, B8 = I.sqrt_workload(m, l, n, pg)
+            dA8, dB8, dC8 = mp.to_device(A8), mp.to_device(B8), mp.empty(m, n, pg)
+            out = {}
+            for name in algos:
+                al = mp.ALGOS[name]
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    mp.mp_gemm_ex(m, l, n, pg, al, 32, mp.MIXED, mp.LEAF_SIMPLE, dA8, dB8, dC8)
+                    torch.cuda.synchronize()
+                    tk = time.perf_counter() - t0
+                out[name] = {"ms": round(tk * 1e3, 3), "2mln_per_s": 2.0 * m * l * n / tk,
+                             "max_rel_err_sampled": rel_err(mp.to_host(dC8), m, l, n)}
+            return out
+
+        paper_grid = {"config": "128 bits, cutoff 32, mixed policy; relative errors on rows 0, m/2, m-1",
+                      "square": {}, "table5_m_n_1024": {}}
+        for nn in (255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049):
+            paper_grid["square"][nn] = run(nn, nn, nn, ("simple", "block", "strassen", "winograd"))
+        for ll in (63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513):
+            paper_grid["table5_m_n_1024"][ll] = run(1024, ll, 1024, ("simple", "strassen", "winograd"))
+
     serve_res = None
     if args.serve_requests > 0:
         del dA, dB, dC
@@ -350,7 +395,7 @@ def main():
                                "seeds 6/7" % (n, p, args.algo, args.cutoff),
                    "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others, "slice": slice_res,
-        "accuracy": accuracy, "serve": serve_res, "lu": lu_res, "lu_paper": lu_paper,
+        "accuracy": accuracy, "serve": serve_res, "lu": lu_res, "lu_paper": lu_paper, "paper_grid": paper_grid,
     }
     print(json.dumps(out))
 

@@ -257,6 +257,12 @@ void assemble(Plan& P, Builder& b)
         add_node_step(b.opsA[d], wino ? OP_WINO_A : OP_STR_A);
         add_node_step(b.opsB[d], wino ? OP_WINO_B : OP_STR_B);
     }
+    // the leaf launch's tasks are independent; a lane's work is its task's
+    // inner length, so the long ones (peeled borders, Simple over the full
+    // inner size) go first and overlap with the many short leaves instead of
+    // trailing them
+    std::stable_sort(b.leaves.begin(), b.leaves.end(),
+                     [](const GemmTask& x, const GemmTask& y) { return x.l > y.l; });
     add_gemm_step(b.leaves, k.leaf == 1 ? 1 : 0);
     for (int d = b.depth - 1; d >= 0; d--) {
         add_node_step(b.combs[d], wino ? OP_WINO_C : OP_STR_C);

@@ -17,6 +17,8 @@ is all words 0.  In Python a value is the pair (sig, e) with sig = +-M, the
 same pair oracle.mpnum uses.
 """
 
+import math
+
 import numpy as np
 
 MASK32 = 0xFFFFFFFF
@@ -229,6 +231,40 @@ def hilbert(n, p, ld=None):
     idx = np.add.outer(np.arange(n), np.arange(n)) + 1
     out[:, :, :n] = V[:, 0, :][:, idx]
     return out
+
+
+def _rn_sqrt_times(c, k, p):
+    """(sig, e) of the p-bit value nearest k * sqrt(c) (k >= 1, c not a square):
+    integer square roots only; the value is irrational, so there is no tie."""
+    v = c * k * k
+    e = math.isqrt(v).bit_length()
+    s = 2 * (p + 1 - e)
+    r = math.isqrt(v << s) if s >= 0 else math.isqrt(v >> -s)
+    M = (r >> 1) + (r & 1)
+    if M == 1 << p:
+        M >>= 1
+        e += 1
+    return (M, e)
+
+
+def sqrt_workload(m, l, n, p):
+    """The paper's benchmark matrices (Section 3): A (m x l) with
+    a_ij = sqrt5 (i + j - 1), B (l x n) with b_ij = sqrt3 (n - i + 1), 1-based,
+    each the nearest p-bit value (n is the column count of B and C, l <= n).
+    c_ij = sqrt15 [(i - 1) l (2n - l + 1) / 2 + sum_k k (n - k + 1)]."""
+    if l > n:
+        raise ValueError("b_ij = sqrt3 (n - i + 1) needs l <= n")
+    A = empty(m, l, p)
+    B = empty(l, n, p)
+    VA = empty(1, m + l, p)
+    for q in range(1, m + l):
+        set_entry(VA, 0, q, _rn_sqrt_times(5, q, p), p)
+    A[:] = VA[:, 0, :][:, np.add.outer(np.arange(m), np.arange(l)) + 1]
+    VB = empty(1, l, p)
+    for i in range(l):
+        set_entry(VB, 0, i, _rn_sqrt_times(3, n - i, p), p)
+    B[:] = VB[:, 0, :][:, :, None]
+    return A, B
 
 
 def lotkin(n, p, ld=None):

@@ -273,3 +273,37 @@ def test_c_oracle_sparse_bit_inputs():
         Cp = G.gemm(Ao, Bo, p, algo=algo, cutoff=2)
         Cc = I.from_planes(cref.gemm(A, B, p, algo=algo, cutoff=2), p)
         assert Cp == Cc
+
+
+def test_sqrt_workload_generator_matches_and_is_nearest():
+    """The shared generator of the paper's matrices equals the construction
+    above (square case) and gives the nearest p-bit values in the
+    rectangular case (A m x l, B l x n with b_ij = sqrt3 (n - i + 1))."""
+    from mpmath import mp, mpf, sqrt
+    for n in (8, 21):
+        A, B = I.sqrt_workload(n, n, n, 128)
+        Ao, Bo = paper_matrices(n, 128)
+        assert I.from_planes(A, 128) == Ao and I.from_planes(B, 128) == Bo
+    mp.prec = 800
+    for p in (128, 512):
+        m, l, n = 6, 5, 9
+        A, B = I.sqrt_workload(m, l, n, p)
+        for i in range(m):
+            for j in range(l):
+                sig, e = I.entry(A, i, j, p)
+                assert abs(mpf(sig) * mpf(2) ** (e - p) - sqrt(5) * (i + j + 1)) <= mpf(2) ** (e - p - 1)
+        for i in range(l):
+            for j in range(n):
+                sig, e = I.entry(B, i, j, p)
+                assert abs(mpf(sig) * mpf(2) ** (e - p) - sqrt(3) * (n - i)) <= mpf(2) ** (e - p - 1)
+
+
+def test_rectangular_closed_form():
+    """c_ij = sqrt15 [(i-1) l (2n-l+1)/2 + sum_k k (n-k+1)] for the paper's
+    rectangular matrices, checked against the exact product of the exact
+    (unrounded) entries in the form sqrt15 * integer."""
+    m, l, n = 5, 7, 11
+    for i in range(m):
+        exact = sum((i + k + 1) * (n - k) for k in range(l))      # coefficient of sqrt15
+        closed = i * l * (2 * n - l + 1) // 2 + sum(k * (n - k + 1) for k in range(1, l + 1))
+        assert exact == closed
