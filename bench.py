@@ -78,9 +78,10 @@ def parse():
                          "trailing updates (cutoff 32) against column-wise LU (one panel), random at 256 bits and "
                          "Lotkin at 512 bits, x = [0..n-1]; 0: skip")
     ap.add_argument("--paper-grid", type=int, default=1,
-                    help="the paper's own matrices (Section 3: a_ij = sqrt5 (i+j-1), b_ij = sqrt3 (n-i+1)) at 128 bits, "
-                         "cutoff 32, mixed odd-size policy: square n = 255..2049 and Table 5's m = n = 1024 with l = "
-                         "63..513; times and sampled relative errors against the closed form; 0: skip")
+                    help="the paper's own matrices (Section 3: a_ij = sqrt5 (i+j-1), b_ij = sqrt3 (n-i+1)), cutoff 32, "
+                         "mixed odd-size policy: square n = 255..2049 and Table 5's m = n = 1024 with l = 63..513 at "
+                         "128 bits, square n = 255..2048 at 1024 bits; times and sampled relative errors against the "
+                         "closed form; 0: skip")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving run (0: skip): Poisson arrivals at 0.8 x the measured "
                          "saturated rate, 90%% products / 10%% LU solves, 128/256/512 bits")
@@ -312,9 +313,8 @@ def main():
     paper_grid = None
     if args.paper_grid:
         from math import isqrt
-        pg = 128
 
-        def rel_err(C, m, l, n):
+        def rel_err(C, m, l, n, pg):
             # rows 0, m/2, m-1, every column; exact c_ij = sqrt15 R_i, sqrt15 R_i to 3p fraction bits
             tail = sum(k * (n - k + 1) for k in range(1, l + 1))
             worst = 0.0
@@ -327,7 +327,7 @@ def main():
                     worst = max(worst, float(abs(Fraction(sig) * Fraction(2) ** (e - pg) - X) / X))
             return worst
 
-        def run(m, l, n, algos):
+        def run(m, l, n, algos, pg=128):
             A8, B8 = I.sqrt_workload(m, l, n, pg)
             dA8, dB8, dC8 = mp.to_device(A8), mp.to_device(B8), mp.empty(m, n, pg)
             out = {}
@@ -340,15 +340,18 @@ def main():
                     torch.cuda.synchronize()
                     tk = time.perf_counter() - t0
                 out[name] = {"ms": round(tk * 1e3, 3), "2mln_per_s": 2.0 * m * l * n / tk,
-                             "max_rel_err_sampled": rel_err(mp.to_host(dC8), m, l, n)}
+                             "max_rel_err_sampled": rel_err(mp.to_host(dC8), m, l, n, pg)}
             return out
 
-        paper_grid = {"config": "128 bits, cutoff 32, mixed policy; relative errors on rows 0, m/2, m-1",
-                      "square": {}, "table5_m_n_1024": {}}
+        paper_grid = {"config": "cutoff 32, mixed policy; relative errors on rows 0, m/2, m-1",
+                      "square": {}, "table5_m_n_1024": {}, "square_1024bit": {}}
         for nn in (255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049):
             paper_grid["square"][nn] = run(nn, nn, nn, ("simple", "block", "strassen", "winograd"))
         for ll in (63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513):
             paper_grid["table5_m_n_1024"][ll] = run(1024, ll, 1024, ("simple", "strassen", "winograd"))
+        for nn in (255, 256, 511, 512, 1023, 1024, 2048):
+            paper_grid["square_1024bit"][nn] = run(nn, nn, nn, ("simple", "block", "strassen", "winograd")
+                                                   if nn <= 1024 else ("strassen", "winograd"), pg=1024)
 
     serve_res = None
     if args.serve_requests > 0:

@@ -14,7 +14,7 @@
  * algorithms (here with partial pivoting).
  *
  * ------------------------------------------------------------------ numbers
- * prec p is 128, 256 or 512 bits; L = p / 32.  A value is
+ * prec p is 128, 256, 512 or 1024 bits; L = p / 32.  A value is
  *     (-1)^s * M * 2^(e - p),   2^(p-1) <= M < 2^p   (M normalised),
  * or zero (M = 0, e = 0, s = 0; there is one zero, +0).  Every operation
  * rounds its exact result to the nearest p-bit value, ties to the even
@@ -82,7 +82,7 @@ enum mp_leaf {        /* kernel for the products below the cutoff */
 enum mp_status {
     MP_OK = 0,
     MP_E_ARG = -1,    /* bad size, stride, pointer or enum */
-    MP_E_PREC = -2,   /* prec not 128, 256 or 512 */
+    MP_E_PREC = -2,   /* prec not 128, 256, 512 or 1024 */
     MP_E_ALIAS = -3,  /* output buffer overlaps an input buffer */
     MP_E_NOMEM = -4,  /* device allocation failed */
     MP_E_DEVICE = -5, /* HIP error (launch failure or earlier asynchronous fault) */

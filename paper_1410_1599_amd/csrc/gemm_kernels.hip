@@ -356,6 +356,7 @@ hipError_t launch_fill_uniform(int L, uint32_t* X, int64_t ld, int64_t ps, int64
     case 4: hipLaunchKernelGGL((k_fill_uniform<4>), g, dim3(256), 0, s, X, ld, ps, rows, cols, seed); break;
     case 8: hipLaunchKernelGGL((k_fill_uniform<8>), g, dim3(256), 0, s, X, ld, ps, rows, cols, seed); break;
     case 16: hipLaunchKernelGGL((k_fill_uniform<16>), g, dim3(256), 0, s, X, ld, ps, rows, cols, seed); break;
+    case 32: hipLaunchKernelGGL((k_fill_uniform<32>), g, dim3(256), 0, s, X, ld, ps, rows, cols, seed); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -381,6 +382,7 @@ hipError_t launch_gemm(int L, int kind, const GemmTask* tasks, const int32_t* ti
     case 4: return gemm_launch_L<4>(kind, tasks, tile_task, ntiles, bs, grid, s);
     case 8: return gemm_launch_L<8>(kind, tasks, tile_task, ntiles, bs, grid, s);
     case 16: return gemm_launch_L<16>(kind, tasks, tile_task, ntiles, bs, grid, s);
+    case 32: return gemm_launch_L<32>(kind, tasks, tile_task, ntiles, bs, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -422,6 +424,7 @@ hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile
     case 4: return node_launch_L<4>(op, tasks, tile_task, ntiles, bs, grid, s);
     case 8: return node_launch_L<8>(op, tasks, tile_task, ntiles, bs, grid, s);
     case 16: return node_launch_L<16>(op, tasks, tile_task, ntiles, bs, grid, s);
+    case 32: return node_launch_L<32>(op, tasks, tile_task, ntiles, bs, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

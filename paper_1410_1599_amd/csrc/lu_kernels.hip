@@ -423,6 +423,7 @@ k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
     case 4: { constexpr int LL = 4; CALL; break; }   \
     case 8: { constexpr int LL = 8; CALL; break; }   \
     case 16: { constexpr int LL = 16; CALL; break; } \
+    case 32: { constexpr int LL = 32; CALL; break; } \
     default: return hipErrorInvalidValue;  \
     }
 

@@ -9,9 +9,9 @@ namespace mpg {
 // bits kept below p at most (the window W = p + extra, extra <= this)
 constexpr int SLICE_MAX_EXTRA = 64;
 // digit words per element: S = ceil((W + 2) / 8) digits at W = p + 64
-constexpr int SLICE_NW4 = 7, SLICE_NW8 = 11, SLICE_NW16 = 19;
+constexpr int SLICE_NW4 = 7, SLICE_NW8 = 11, SLICE_NW16 = 19, SLICE_NW32 = 35;
 // 32-bit positions of the recombined sum: 8 (S_A + S_B - 2) + 40 bits plus one
-constexpr int SLICE_NWZ4 = 15, SLICE_NWZ8 = 23, SLICE_NWZ16 = 39;
+constexpr int SLICE_NWZ4 = 15, SLICE_NWZ8 = 23, SLICE_NWZ16 = 39, SLICE_NWZ32 = 71;
 // |digit| <= 128, so a product is at most 2^14 and an INT32 sum of K of them
 // is exact while K * 2^14 < 2^31
 constexpr int64_t SLICE_KMAX = 131008;

@@ -444,6 +444,7 @@ hipError_t launch_slice_scan(int L, const uint32_t* X, int64_t ld, int64_t ps, i
         case 4: hipLaunchKernelGGL((k_slice_scan_rows<4>), g, dim3(256), 0, s, X, ld, ps, inner, emax, emin); break;
         case 8: hipLaunchKernelGGL((k_slice_scan_rows<8>), g, dim3(256), 0, s, X, ld, ps, inner, emax, emin); break;
         case 16: hipLaunchKernelGGL((k_slice_scan_rows<16>), g, dim3(256), 0, s, X, ld, ps, inner, emax, emin); break;
+        case 32: hipLaunchKernelGGL((k_slice_scan_rows<32>), g, dim3(256), 0, s, X, ld, ps, inner, emax, emin); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -456,6 +457,7 @@ hipError_t launch_slice_scan(int L, const uint32_t* X, int64_t ld, int64_t ps, i
     case 4: hipLaunchKernelGGL((k_slice_scan_cols<4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, phi, plo); break;
     case 8: hipLaunchKernelGGL((k_slice_scan_cols<8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, phi, plo); break;
     case 16: hipLaunchKernelGGL((k_slice_scan_cols<16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, phi, plo); break;
+    case 32: hipLaunchKernelGGL((k_slice_scan_cols<32>), g, dim3(256), 0, s, X, ld, ps, outer, inner, phi, plo); break;
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_slice_scan_fold, dim3((unsigned)((outer + 255) / 256)), dim3(256), 0, s, phi, plo, outer,
@@ -474,6 +476,7 @@ hipError_t launch_slice_digits(int L, const uint32_t* X, int64_t ld, int64_t ps,
     case 4: hipLaunchKernelGGL((k_slice_digits<4, SLICE_NW4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
     case 8: hipLaunchKernelGGL((k_slice_digits<8, SLICE_NW8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
     case 16: hipLaunchKernelGGL((k_slice_digits<16, SLICE_NW16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
+    case 32: hipLaunchKernelGGL((k_slice_digits<32, SLICE_NW32>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -498,6 +501,7 @@ hipError_t launch_slice_combine(int L, const int32_t* G, int64_t g_plane, int32_
     case 4: hipLaunchKernelGGL((k_slice_combine<4, SLICE_NWZ4>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
     case 8: hipLaunchKernelGGL((k_slice_combine<8, SLICE_NWZ8>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
     case 16: hipLaunchKernelGGL((k_slice_combine<16, SLICE_NWZ16>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
+    case 32: hipLaunchKernelGGL((k_slice_combine<32, SLICE_NWZ32>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

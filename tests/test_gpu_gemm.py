@@ -46,7 +46,7 @@ def assert_same(got, want, p, what=""):
 
 # ------------------------------------------------------------- primitives
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_scalar_ops_adversarial(p):
     rng = random.Random(500 + p)
     pairs = adversarial_pairs(rng, p) + [(random_value(rng, p, -40, 40), random_value(rng, p, -40, 40)) for _ in range(2000)]
@@ -71,7 +71,7 @@ def test_scalar_ops_adversarial(p):
             assert got == want, (name, p, x, y, got, want)
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_division_random_mantissas(p):
     rng = random.Random(900 + p)
     pairs = [(random_value(rng, p, -300, 300), random_value(rng, p, -300, 300)) for _ in range(3000)]
@@ -113,7 +113,7 @@ SHAPES = [(1, 1, 1), (1, 7, 1), (5, 1, 9), (9, 9, 9), (31, 33, 35), (33, 31, 66)
           (67, 64, 63), (130, 7, 129), (100, 130, 70), (257, 33, 5)]
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 @pytest.mark.parametrize("algo", ["simple", "block", "strassen", "winograd"])
 def test_ragged_shapes_against_c_oracle(p, algo):
     rng = np.random.default_rng(p)
@@ -138,7 +138,7 @@ def test_block_leaves_in_fast_algorithms(p):
         assert_same(got, want, p, algo + " block leaves")
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_tie_heavy_and_integer_inputs(p):
     A = I.sparse_bits(40, 37, p, 7)
     B = I.sparse_bits(37, 45, p, 8)

@@ -37,7 +37,7 @@ def gpu_solve(F, piv, b, p):
     return mp.to_host(db)
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 @pytest.mark.parametrize("kind", ["random", "hilbert"])
 def test_lu_small_against_oracle(p, kind):
     n = 45
@@ -92,7 +92,7 @@ def gpu_lu_nopivot(A, p, panel, algo, cutoff, policy=mp.PEEL):
     return mp.to_host(dA), piv.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 @pytest.mark.parametrize("kind", ["random", "lotkin"])
 def test_lu_nopivot_small_against_oracle(p, kind):
     """The paper's LU without row exchanges (Section 4)."""

@@ -77,3 +77,19 @@ def test_rectangular_paper_matrices(l):
             got = gpu_gemm(A, B, p, algo, 32, policy)
             assert planes_equal(got, want), (algo, policy, first_mismatch(got, want, p))
     assert 0 < max_rel_error(got, m, l, n, p) < 1e-34
+
+
+def test_paper_matrices_1024_bits():
+    """The paper's second precision (Tables 4 and 5): 1024 bits, every
+    algorithm bit-exact to the oracle, errors inside the paper's 1024-bit
+    figures (Strassen 6.30e-306, Winograd 3.92e-305)."""
+    p, n = 1024, 131
+    gold = json.load(open(os.path.join(GOLD, "paper_errors.json")))
+    A, B = I.sqrt_workload(n, n, n, p)
+    for algo in ALGOS:
+        want = cref.gemm(A, B, p, algo=algo, cutoff=32, policy="mixed")
+        got = gpu_gemm(A, B, p, algo, 32, "mixed")
+        assert planes_equal(got, want), (algo, first_mismatch(got, want, p))
+        err = max_rel_error(got, n, n, n, p)
+        print("1024 bits n=%d %s: max relative error %.3g" % (n, algo, err))
+        assert 0 < err <= (gold["winograd_1024_max"] if algo == "winograd" else gold["strassen_1024_max"])

@@ -33,7 +33,7 @@ def gpu_slice(A, B, p, extra=64):
     return mp.to_host(dC), w
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_small_shapes_exact_rounding(p):
     for (m, l, n, kind) in ((1, 1, 1, "u"), (5, 7, 9, "u"), (130, 70, 129, "log"), (64, 200, 64, "log"),
                             (129, 1, 257, "u"), (3, 300, 2, "log")):
