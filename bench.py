@@ -204,9 +204,24 @@ def main():
         ts = (time.perf_counter() - t0) / args.slice_steps
         mp.mp_profile(False)
         srecs = mp.mp_profile_read()
-        mm = [r for r in srecs if r["kind"] == 2]
+        # first pass of the early stop (diagonals u >= u0, every tile): the
+        # dominant launch; the second pass runs only for undecided tiles
+        mm = [r for r in srecs if r["kind"] == 2 and r["op"] == 0]
+        mm2 = [r for r in srecs if r["kind"] == 2 and r["op"] == 1]
         mm_ms = sum(r["ms"] for r in mm) / max(1, len(mm))
         mm_tops = mm[0]["units"] / (mm_ms * 1e-3) / 1e12 if mm else 0.0
+        u0, ndiag, recomputed, ntiles, _ = mp.mp_slice_last()
+        # the same product computing every diagonal in one pass, for comparison
+        mp.mp_set_slice_guard(-1)
+        mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.slice_steps):
+            mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
+        torch.cuda.synchronize()
+        ts_one = (time.perf_counter() - t1) / args.slice_steps
+        mp.mp_set_slice_guard(32)
+        mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
         slice_res = {
             "value": 2.0 * n ** 3 / ts, "unit": "2mln/s", "ms_per_step": round(ts * 1e3, 3),
             "speedup_vs_limb": round(ms / (ts * 1e3), 3), "windows": list(win),
@@ -216,6 +231,9 @@ def main():
                          "frac": round(mm_tops / 5000.0, 4), "kernel": "k_slice_gemm (v_mfma_i32_32x32x32_i8)",
                          "launch_ms": round(mm_ms, 3)},
             "other_ms": round(sum(r["ms"] for r in srecs if r["kind"] == 3) / args.slice_steps, 3),
+            "early_stop": {"u0": u0, "diagonals": ndiag, "tiles_recomputed": recomputed, "tiles": ntiles,
+                           "second_pass_ms": round(sum(r["ms"] for r in mm2) / args.slice_steps, 3),
+                           "one_pass_ms_per_step": round(ts_one * 1e3, 3)},
         }
         slice_host = mp.to_host(dS)
         del dS

@@ -190,6 +190,27 @@ int mp_gemm_slice(int64_t m, int64_t l, int64_t n, int prec, int extra,
                   uint32_t *C, int64_t ldc, int64_t psc, int32_t *window_out);
 
 /*
+ * Early stop of mp_gemm_slice (the same result, less matrix-core work).  The
+ * exact sum is sum_u 256^u G_u over digit-pair diagonals u.  A first pass
+ * computes the diagonals u >= u0 only and rounds every entry whose rounding the
+ * omitted part, below a proven bound 2^D, cannot change (its bits between 2^D
+ * and its round bit are neither all zero nor all one); a second pass computes
+ * the diagonals u < u0 and rounds from all of them for the 256 x 256 output
+ * tiles that hold any other entry.  u0 leaves `guard_bits` bits between 2^D
+ * and the last kept bit of an entry of magnitude 2^(W_A+W_B) (the largest
+ * product of two window-scaled entries): more guard bits, fewer recomputed
+ * tiles on sums that cancel.  guard_bits < 0 computes every diagonal in one
+ * pass.  Default 32.  Process-wide setting; MP_E_ARG above 2^20.
+ */
+int mp_set_slice_guard(int guard_bits);
+/*
+ * What the last mp_gemm_slice on this process did, in info5 (host, 5 int32):
+ * u0 (0: one pass), the number of diagonals, the output tiles recomputed by the
+ * second pass, the number of output tiles, and D.
+ */
+int mp_slice_last(int32_t *info5);
+
+/*
  * LU decomposition with partial pivoting of the n x n matrix A in place
  * (Section 4, blocked with panel width K, trailing update A22 := A22 - L21 U12
  * with the product formed by `algo`; the paper's LU does not pivot, this one

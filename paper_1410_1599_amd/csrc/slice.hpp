@@ -32,9 +32,11 @@ hipError_t launch_slice_digits(int L, const uint32_t* X, int64_t ld, int64_t ps,
                                int64_t outer_pad, int64_t kpad, hipStream_t s);
 hipError_t launch_slice_gemm(const SliceTask* tasks, int64_t ntasks, const int8_t* A8, const int8_t* B8, int32_t* G,
                              int64_t a_plane, int64_t b_plane, int64_t g_plane, int32_t kpad, int32_t npad,
-                             hipStream_t s);
+                             const int32_t* flags, int32_t tj_n, hipStream_t s);
+hipError_t launch_slice_fill(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 hipError_t launch_slice_combine(int L, const int32_t* G, int64_t g_plane, int32_t npad, const int32_t* slot_begin,
                                 int32_t ndiag, const int32_t* ea, const int32_t* fb, int32_t WA, int32_t WB,
-                                uint32_t* C, int64_t ldc, int64_t psc, int64_t m, int64_t n, hipStream_t s);
+                                uint32_t* C, int64_t ldc, int64_t psc, int64_t m, int64_t n, int32_t mode,
+                                int32_t ulo, int32_t D, int32_t* flags, int32_t tj_n, hipStream_t s);
 
 }  // namespace mpg

@@ -247,11 +247,14 @@ __device__ __forceinline__ void lds_dma16(const int8_t* src, uint32_t lds)
 __global__ void __launch_bounds__(GT)
 k_slice_gemm(const SliceTask* __restrict__ tasks, const int8_t* __restrict__ A8, const int8_t* __restrict__ B8,
              int32_t* __restrict__ G, int64_t a_plane, int64_t b_plane, int64_t g_plane, int32_t kpad,
-             int32_t npad)
+             int32_t npad, const int32_t* __restrict__ flags, int32_t tj_n)
 {
     __shared__ __attribute__((aligned(16))) int8_t sA[NST][TM * TKK];
     __shared__ __attribute__((aligned(16))) int8_t sB[NST][TN * TKK];
     const SliceTask T = tasks[blockIdx.x];
+    // second pass of the certified early stop: only tiles that hold an entry
+    // whose rounding the first pass could not decide
+    if (flags != nullptr && flags[T.ti * tj_n + T.tj] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wy = wave >> 2, wx = wave & 3;
     v16i acc[FA][FB];
@@ -338,18 +341,34 @@ k_slice_gemm(const SliceTask* __restrict__ tasks, const int8_t* __restrict__ A8,
 
 // ------------------------------------------------------------------ recombination
 
-// c_ij = RN_p(2^(e_i + f_j - W_A - W_B) * sum_u 256^u G_u,ij).  slot_begin[u] ..
-// slot_begin[u+1] are the G slots of diagonal u.  The sum is kept as signed
-// 64-bit partial sums per 32-bit position (each below 2^58), carried once.
+// c_ij = RN_p(2^(e_i + f_j - W_A - W_B) * Z), Z = sum_u 256^u G_u,ij.
+// slot_begin[u] .. slot_begin[u+1] are the G slots of diagonal u.  The sum is
+// kept as signed 64-bit partial sums per 32-bit position (each below 2^58),
+// carried once.
+//
+// mode 0: every diagonal.  mode 1: only the diagonals u >= ulo (the first pass
+// of the certified early stop); the omitted part is below 2^D in magnitude, so
+// Z lies within 2^D of the partial sum V.  With sh the position of V's last
+// kept bit, RN(Z) = RN(V) when sh - 1 > D and the bits D .. sh-2 of |V| are
+// neither all zero nor all one: then V's tail below the kept bits stays more
+// than 2^D away from zero, from the midpoint and from a full unit, so neither
+// the kept bits, the round bit, nor a tie can change (nor the bit length or
+// the sign, since |V| >= 2^(p-1+sh) > 2^D).  Such an entry is written; any
+// other marks its tile in flags.  mode 2: every diagonal, only for the
+// entries of flagged tiles.
 template <int L, int NWZ>
 __global__ void __launch_bounds__(256)
 k_slice_combine(const int32_t* __restrict__ G, int64_t g_plane, int32_t npad, const int32_t* __restrict__ slot_begin,
                 int32_t ndiag, const int32_t* __restrict__ ea, const int32_t* __restrict__ fb, int32_t WA, int32_t WB,
-                uint32_t* __restrict__ C, int64_t ldc, int64_t psc, int64_t m, int64_t n)
+                uint32_t* __restrict__ C, int64_t ldc, int64_t psc, int64_t m, int64_t n, int32_t mode, int32_t ulo,
+                int32_t D, int32_t* __restrict__ flags, int32_t tj_n)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= m * n) return;
     const int64_t i = e / n, j = e % n;
+    const int64_t tile = (i / SLICE_TILE_M) * tj_n + j / SLICE_TILE_N;
+    if (mode == 2 && flags[tile] == 0) return;
+    const int32_t u_from = mode == 1 ? ulo : 0;
     int64_t acc[NWZ];
 #pragma unroll
     for (int q = 0; q < NWZ; q++) acc[q] = 0;
@@ -359,6 +378,7 @@ k_slice_combine(const int32_t* __restrict__ G, int64_t g_plane, int32_t npad, co
         for (int b = 0; b < 4; b++) {
             const int u = 4 * q + b;
             if (u >= ndiag) break;
+            if (u < u_from) continue;
             for (int sl = slot_begin[u]; sl < slot_begin[u + 1]; sl++)
                 acc[q] += (int64_t)G[(int64_t)sl * g_plane + i * npad + j] * ((int64_t)1 << (8 * b));
         }
@@ -383,13 +403,39 @@ k_slice_combine(const int32_t* __restrict__ G, int64_t g_plane, int32_t npad, co
 #pragma unroll
     for (int q = 0; q < NWZ; q++) top = Z[q] ? q : top;
     MP<L> r = mp_zero<L>();
+    int32_t b = 0;
     if (top >= 0) {
         uint32_t tw = 0;
 #pragma unroll
         for (int q = 0; q < NWZ; q++) tw = (q == top) ? Z[q] : tw;
-        const int32_t b = 32 * top + 32 - (int32_t)__builtin_clz(tw);    // bit length of |Z|
-        // keep bits [b - p, b): shift right by sh = b - p (may be negative)
-        const int32_t sh = b - 32 * L;
+        b = 32 * top + 32 - (int32_t)__builtin_clz(tw);    // bit length of |Z|
+    }
+    // keep bits [b - p, b): shift right by sh = b - p (may be negative)
+    const int32_t sh = b - 32 * L;
+    if (mode == 1) {
+        bool certain = false;
+        if (top >= 0 && sh - 1 > D) {
+            uint32_t any1 = 0, any0 = 0;
+#pragma unroll
+            for (int t = 0; t < NWZ; t++) {
+                const int32_t lo = 32 * t;
+                const int32_t a = D > lo ? D : lo;
+                const int32_t z = (sh - 1) < lo + 32 ? (sh - 1) : lo + 32;
+                if (a < z) {
+                    const uint32_t w = (uint32_t)(z - a);
+                    const uint32_t mask = (w >= 32u ? 0xffffffffu : ((1u << w) - 1u)) << (uint32_t)(a - lo);
+                    any1 |= Z[t] & mask;
+                    any0 |= ~Z[t] & mask;
+                }
+            }
+            certain = any1 != 0 && any0 != 0;
+        }
+        if (!certain) {
+            flags[tile] = 1;
+            return;
+        }
+    }
+    if (top >= 0) {
         uint32_t M[L];
 #pragma unroll
         for (int k = 0; k < L; k++) {
@@ -430,6 +476,12 @@ k_slice_combine(const int32_t* __restrict__ G, int64_t g_plane, int32_t npad, co
         r.s = neg ? 1u : 0u;
     }
     store<L>(C, psc, i * ldc + j, r);
+}
+
+__global__ void __launch_bounds__(256) k_slice_fill(int32_t* __restrict__ p, int64_t count, int32_t v)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < count) p[e] = v;
 }
 
 }  // namespace
@@ -484,24 +536,32 @@ hipError_t launch_slice_digits(int L, const uint32_t* X, int64_t ld, int64_t ps,
 
 hipError_t launch_slice_gemm(const SliceTask* tasks, int64_t ntasks, const int8_t* A8, const int8_t* B8, int32_t* G,
                              int64_t a_plane, int64_t b_plane, int64_t g_plane, int32_t kpad, int32_t npad,
-                             hipStream_t s)
+                             const int32_t* flags, int32_t tj_n, hipStream_t s)
 {
     if (ntasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_slice_gemm, dim3((unsigned)ntasks), dim3(GT), 0, s, tasks, A8, B8, G, a_plane, b_plane,
-                       g_plane, kpad, npad);
+                       g_plane, kpad, npad, flags, tj_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_fill(int32_t* p, int64_t count, int32_t v, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slice_fill, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
     return hipGetLastError();
 }
 
 hipError_t launch_slice_combine(int L, const int32_t* G, int64_t g_plane, int32_t npad, const int32_t* slot_begin,
                                 int32_t ndiag, const int32_t* ea, const int32_t* fb, int32_t WA, int32_t WB,
-                                uint32_t* C, int64_t ldc, int64_t psc, int64_t m, int64_t n, hipStream_t s)
+                                uint32_t* C, int64_t ldc, int64_t psc, int64_t m, int64_t n, int32_t mode,
+                                int32_t ulo, int32_t D, int32_t* flags, int32_t tj_n, hipStream_t s)
 {
     const dim3 g((unsigned)((m * n + 255) / 256));
     switch (L) {
-    case 4: hipLaunchKernelGGL((k_slice_combine<4, SLICE_NWZ4>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
-    case 8: hipLaunchKernelGGL((k_slice_combine<8, SLICE_NWZ8>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
-    case 16: hipLaunchKernelGGL((k_slice_combine<16, SLICE_NWZ16>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
-    case 32: hipLaunchKernelGGL((k_slice_combine<32, SLICE_NWZ32>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n); break;
+    case 4: hipLaunchKernelGGL((k_slice_combine<4, SLICE_NWZ4>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n, mode, ulo, D, flags, tj_n); break;
+    case 8: hipLaunchKernelGGL((k_slice_combine<8, SLICE_NWZ8>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n, mode, ulo, D, flags, tj_n); break;
+    case 16: hipLaunchKernelGGL((k_slice_combine<16, SLICE_NWZ16>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n, mode, ulo, D, flags, tj_n); break;
+    case 32: hipLaunchKernelGGL((k_slice_combine<32, SLICE_NWZ32>), g, dim3(256), 0, s, G, g_plane, npad, slot_begin, ndiag, ea, fb, WA, WB, C, ldc, psc, m, n, mode, ulo, D, flags, tj_n); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

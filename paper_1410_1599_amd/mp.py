@@ -61,6 +61,8 @@ def _load():
         "mp_release_workspace": ([], i32),
         "mp_profile": ([i32], i32),
         "mp_gemm_slice": ([i64, i64, i64, i32, i32] + mat * 3 + [i32p], i32),
+        "mp_set_slice_guard": ([i32], i32),
+        "mp_slice_last": ([i32p], i32),
         "mp_set_graph_mode": ([i32], i32),
         "mp_fill_uniform": ([i64, i64, i32, vp, i64, i64, ctypes.c_uint64], i32),
         "mp_gemm_batched": ([i32, i64p, i64p, i64p, i32, i32, i32] + [ctypes.POINTER(vp), i64p, i64p] * 3, i32),
@@ -218,6 +220,17 @@ def mp_gemm_slice(m, l, n, prec, extra, A, B, C):
     w = (ctypes.c_int * 2)()
     _check(lib.mp_gemm_slice(m, l, n, prec, int(extra), *_mat(A), *_mat(B), *_mat(C), w))
     return w[0], w[1]
+
+
+def mp_set_slice_guard(guard_bits):
+    return _check(lib.mp_set_slice_guard(int(guard_bits)))
+
+
+def mp_slice_last():
+    """(u0, diagonals, tiles recomputed, tiles, D) of the last slice product."""
+    w = (ctypes.c_int * 5)()
+    _check(lib.mp_slice_last(w))
+    return tuple(int(x) for x in w)
 
 
 def mp_release_workspace():

@@ -143,3 +143,76 @@ def test_n2048_p256_ulp_error_of_every_path():
     print("max ulp vs RN(exact) on %d entries: limb Winograd %.1f, limb Block %.1f, slice 0"
           % (len(g["entries"]), worst["winograd"], worst["block"]))
     assert worst["winograd"] >= worst["block"] >= 0
+
+
+# ------------------------------------------------------------------ early stop
+
+def _slice_guard(A, B, p, guard):
+    mp.mp_set_slice_guard(guard)
+    try:
+        C, w = gpu_slice(A, B, p)
+        info = mp.mp_slice_last()
+    finally:
+        mp.mp_set_slice_guard(32)
+    return C, w, info
+
+
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
+def test_early_stop_equals_one_pass(p):
+    """The two-pass product (diagonals u >= u0 first, low diagonals only for
+    undecided tiles) equals the one-pass product bit for bit, with the default
+    guard and with guard 0 (almost every tile recomputed)."""
+    for (m, l, n, kind, seed) in ((300, 96, 290, "log", 51), (257, 64, 513, "u", 53)):
+        gen = I.uniform_pm1 if kind == "u" else (lambda r, c, pp, sd: I.log_uniform(r, c, pp, sd, -20, 20))
+        A, B = gen(m, l, p, seed), gen(l, n, p, seed + 1)
+        C0, w0, info0 = _slice_guard(A, B, p, -1)
+        assert info0[0] == 0
+        for guard in (32, 0):
+            C1, w1, info1 = _slice_guard(A, B, p, guard)
+            assert w1 == w0
+            assert info1[0] > 0 and info1[1] == info0[1], info1
+            assert np.array_equal(C1, C0), (p, (m, l, n), guard, info1)
+        print("p", p, (m, l, n), "guard 0 recomputed", info1[2], "of", info1[3], "tiles")
+
+
+def test_early_stop_recomputes_cancelling_tiles():
+    """Sums that cancel exactly or nearly are undecided after the first pass:
+    their tiles are recomputed from every diagonal and come out correctly
+    rounded (exact zeros as +0); the other tiles are decided at once."""
+    p, L = 256, 8
+    m, l, n, h = 260, 64, 520, 32
+    A = I.uniform_pm1(m, l, p, 61)
+    B = I.uniform_pm1(l, n, p, 62)
+    A[:, :, h:] = A[:, :, :h]
+    # columns 256.. : b_(k+h) = -b_k, so c_ij = 0; odd columns get the last
+    # bit of one entry flipped, so c_ij = +-a_i,l-1 * ulp(b): tiny and nonzero
+    for j in range(256, n):
+        B[:, h:, j] = B[:, :h, j]
+        nz = B[L - 1, h:, j] != 0
+        B[L + 1, h:, j] = np.where(nz, B[L + 1, h:, j] ^ 1, 0)
+        if j % 2:
+            B[0, l - 1, j] ^= 1
+    C, _, info = _slice_guard(A, B, p, 32)
+    assert info[0] > 0
+    assert info[2] == 4 and info[3] == 6, info    # 2 row tiles x column tiles 1, 2
+    C0, _, _ = _slice_guard(A, B, p, -1)
+    assert np.array_equal(C, C0)
+    Ao, Bo = I.from_planes(A, p), I.from_planes(B, p)
+    for i in (0, 129, 259):
+        for j in list(range(0, 8)) + list(range(250, 270)) + list(range(510, 520)):
+            assert I.entry(C, i, j, p) == exact.exact_entry(Ao, Bo, i, j, p), (i, j)
+    zero_cols = [j for j in range(256, n) if j % 2 == 0]
+    assert not C[:, :, zero_cols].any()
+    assert C[:L, :, [j for j in range(257, n, 2)]].any(axis=0).all()
+
+
+def test_early_stop_guard_settings():
+    p = 256
+    A = I.log_uniform(70, 80, p, 71, -20, 20)
+    B = I.log_uniform(80, 60, p, 72, -20, 20)
+    _, _, info = _slice_guard(A, B, p, 1 << 20)
+    assert info[0] == 0
+    _, _, info = _slice_guard(A, B, p, 32)
+    assert 0 < info[0] < info[1] and info[4] > 0
+    with pytest.raises(RuntimeError):
+        mp.mp_set_slice_guard((1 << 20) + 1)
