@@ -15,6 +15,7 @@
 // count (persistent mode): workgroups stride over the tiles.
 #include "launch.hpp"
 #include "mp_arith.hpp"
+#include "node_ops.hpp"
 
 namespace mpg {
 
@@ -179,18 +180,6 @@ k_gemm_block(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ til
 
 // ------------------------------------------------------------------ node passes
 
-template <int L>
-__device__ __forceinline__ MP<L> ld(const Bases& bs, const MatRef& r, int64_t i, int64_t j)
-{
-    return load<L>(base_ptr(bs, r.base) + r.off, r.ps, i * r.ld + j);
-}
-
-template <int L>
-__device__ __forceinline__ void st(const Bases& bs, const MatRef& r, int64_t i, int64_t j, const MP<L>& v)
-{
-    store<L>(base_ptr(bs, r.base) + r.off, r.ps, i * r.ld + j, v);
-}
-
 template <int L, int OP>
 __global__ void __launch_bounds__(NODE_TILE)
 k_node(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
@@ -200,83 +189,7 @@ k_node(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile_task
         const int64_t e = (t - T.tile0) * NODE_TILE + threadIdx.x;
         const int64_t total = (int64_t)T.rows * T.cols;
         if (e >= total) continue;
-        const int64_t i = e / T.cols, j = e % T.cols;
-        if constexpr (OP == OP_ADD) {
-            st<L>(bs, T.out[0], i, j, add_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
-        } else if constexpr (OP == OP_SUB) {
-            st<L>(bs, T.out[0], i, j, sub_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
-        } else if constexpr (OP == OP_MUL) {
-            st<L>(bs, T.out[0], i, j, mul_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
-        } else if constexpr (OP == OP_DIV) {
-            st<L>(bs, T.out[0], i, j, div_rn<L>(ld<L>(bs, T.in[0], i, j), ld<L>(bs, T.in[1], i, j)));
-        } else if constexpr (OP == OP_COPY) {
-            st<L>(bs, T.out[0], i, j, ld<L>(bs, T.in[0], i, j));
-        } else if constexpr (OP == OP_PADCOPY) {
-            const bool in = i < T.aux0 && j < T.aux1;
-            st<L>(bs, T.out[0], i, j, in ? ld<L>(bs, T.in[0], i, j) : mp_zero<L>());
-        } else if constexpr (OP == OP_WINO_A) {
-            // S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2
-            const MP<L> a11 = ld<L>(bs, T.in[0], i, j), a12 = ld<L>(bs, T.in[1], i, j);
-            const MP<L> a21 = ld<L>(bs, T.in[2], i, j), a22 = ld<L>(bs, T.in[3], i, j);
-            const MP<L> s1 = add_rn<L>(a21, a22);
-            const MP<L> s2 = sub_rn<L>(s1, a11);
-            st<L>(bs, T.out[0], i, j, s1);
-            st<L>(bs, T.out[1], i, j, s2);
-            st<L>(bs, T.out[2], i, j, sub_rn<L>(a11, a21));
-            st<L>(bs, T.out[3], i, j, sub_rn<L>(a12, s2));
-        } else if constexpr (OP == OP_WINO_B) {
-            // S5 = B12 - B11, S6 = B22 - S5, S7 = B22 - B12, S8 = S6 - B21
-            const MP<L> b11 = ld<L>(bs, T.in[0], i, j), b12 = ld<L>(bs, T.in[1], i, j);
-            const MP<L> b21 = ld<L>(bs, T.in[2], i, j), b22 = ld<L>(bs, T.in[3], i, j);
-            const MP<L> s5 = sub_rn<L>(b12, b11);
-            const MP<L> s6 = sub_rn<L>(b22, s5);
-            st<L>(bs, T.out[0], i, j, s5);
-            st<L>(bs, T.out[1], i, j, s6);
-            st<L>(bs, T.out[2], i, j, sub_rn<L>(b22, b12));
-            st<L>(bs, T.out[3], i, j, sub_rn<L>(s6, b21));
-        } else if constexpr (OP == OP_WINO_C) {
-            // T1 = M1 + M2, T2 = T1 + M4; C11 = M2 + M3, C12 = (T1 + M5) + M6,
-            // C21 = T2 - M7, C22 = T2 + M5
-            const MP<L> m1 = ld<L>(bs, T.in[0], i, j), m2 = ld<L>(bs, T.in[1], i, j);
-            const MP<L> m3 = ld<L>(bs, T.in[2], i, j), m4 = ld<L>(bs, T.in[3], i, j);
-            const MP<L> m5 = ld<L>(bs, T.in[4], i, j), m6 = ld<L>(bs, T.in[5], i, j);
-            const MP<L> m7 = ld<L>(bs, T.in[6], i, j);
-            const MP<L> t1 = add_rn<L>(m1, m2);
-            const MP<L> t2 = add_rn<L>(t1, m4);
-            st<L>(bs, T.out[0], i, j, add_rn<L>(m2, m3));
-            st<L>(bs, T.out[1], i, j, add_rn<L>(add_rn<L>(t1, m5), m6));
-            st<L>(bs, T.out[2], i, j, sub_rn<L>(t2, m7));
-            st<L>(bs, T.out[3], i, j, add_rn<L>(t2, m5));
-        } else if constexpr (OP == OP_STR_A) {
-            // A11 + A22, A21 + A22, A11 + A12, A21 - A11, A12 - A22
-            const MP<L> a11 = ld<L>(bs, T.in[0], i, j), a12 = ld<L>(bs, T.in[1], i, j);
-            const MP<L> a21 = ld<L>(bs, T.in[2], i, j), a22 = ld<L>(bs, T.in[3], i, j);
-            st<L>(bs, T.out[0], i, j, add_rn<L>(a11, a22));
-            st<L>(bs, T.out[1], i, j, add_rn<L>(a21, a22));
-            st<L>(bs, T.out[2], i, j, add_rn<L>(a11, a12));
-            st<L>(bs, T.out[3], i, j, sub_rn<L>(a21, a11));
-            st<L>(bs, T.out[4], i, j, sub_rn<L>(a12, a22));
-        } else if constexpr (OP == OP_STR_B) {
-            // B11 + B22, B12 - B22, B21 - B11, B11 + B12, B21 + B22
-            const MP<L> b11 = ld<L>(bs, T.in[0], i, j), b12 = ld<L>(bs, T.in[1], i, j);
-            const MP<L> b21 = ld<L>(bs, T.in[2], i, j), b22 = ld<L>(bs, T.in[3], i, j);
-            st<L>(bs, T.out[0], i, j, add_rn<L>(b11, b22));
-            st<L>(bs, T.out[1], i, j, sub_rn<L>(b12, b22));
-            st<L>(bs, T.out[2], i, j, sub_rn<L>(b21, b11));
-            st<L>(bs, T.out[3], i, j, add_rn<L>(b11, b12));
-            st<L>(bs, T.out[4], i, j, add_rn<L>(b21, b22));
-        } else if constexpr (OP == OP_STR_C) {
-            // C11 = ((P1 + P4) - P5) + P7, C12 = P3 + P5, C21 = P2 + P4,
-            // C22 = ((P1 + P3) - P2) + P6
-            const MP<L> p1 = ld<L>(bs, T.in[0], i, j), p2 = ld<L>(bs, T.in[1], i, j);
-            const MP<L> p3 = ld<L>(bs, T.in[2], i, j), p4 = ld<L>(bs, T.in[3], i, j);
-            const MP<L> p5 = ld<L>(bs, T.in[4], i, j), p6 = ld<L>(bs, T.in[5], i, j);
-            const MP<L> p7 = ld<L>(bs, T.in[6], i, j);
-            st<L>(bs, T.out[0], i, j, add_rn<L>(sub_rn<L>(add_rn<L>(p1, p4), p5), p7));
-            st<L>(bs, T.out[1], i, j, add_rn<L>(p3, p5));
-            st<L>(bs, T.out[2], i, j, add_rn<L>(p2, p4));
-            st<L>(bs, T.out[3], i, j, add_rn<L>(sub_rn<L>(add_rn<L>(p1, p3), p2), p6));
-        }
+        node_apply<MP<L>, L, OP>(bs, T, e / T.cols, e % T.cols);
     }
 }
 
@@ -378,6 +291,7 @@ static hipError_t gemm_launch_L(int kind, const GemmTask* tasks, const int32_t* 
 hipError_t launch_gemm(int L, int kind, const GemmTask* tasks, const int32_t* tile_task, int64_t ntiles,
                        const Bases& bs, int64_t grid, hipStream_t s)
 {
+    if (L >= 64) return launch_gemm_wide(L, tasks, tile_task, ntiles, bs, grid, s);   // Block = Simple's order
     switch (L) {
     case 4: return gemm_launch_L<4>(kind, tasks, tile_task, ntiles, bs, grid, s);
     case 8: return gemm_launch_L<8>(kind, tasks, tile_task, ntiles, bs, grid, s);
@@ -420,6 +334,7 @@ static hipError_t node_launch_L(int op, const NodeTask* tasks, const int32_t* ti
 hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,
                        const Bases& bs, int64_t grid, hipStream_t s)
 {
+    if (L >= 64) return launch_node_wide(L, op, tasks, tile_task, ntiles, bs, grid, s);
     switch (L) {
     case 4: return node_launch_L<4>(op, tasks, tile_task, ntiles, bs, grid, s);
     case 8: return node_launch_L<8>(op, tasks, tile_task, ntiles, bs, grid, s);

@@ -430,6 +430,7 @@ k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
 hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
                                 int32_t* piv, int32_t* info, int search, hipStream_t s)
 {
+    if (L >= 64) return launch_lu_pivot_swap_wide(L, bs, a, n, c, j0, je, piv, info, search, s);
     MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_pivot_swap<LL>), dim3(1), dim3(PIV_THREADS), 0, s, bs, a, n, c, j0, je,
                                          piv, info, search));
     return hipGetLastError();
@@ -438,6 +439,7 @@ hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int
 hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, hipStream_t s)
 {
     if (n - c - 1 <= 0) return hipSuccess;
+    if (L >= 64) return launch_lu_eliminate_wide(L, bs, a, n, c, je, s);
     MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_eliminate<LL>), dim3((unsigned)(n - c - 1)), dim3(ELIM_THREADS), 0, s,
                                          bs, a, c, je));
     return hipGetLastError();
@@ -447,6 +449,7 @@ hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t k
                          hipStream_t s)
 {
     if (n - je <= 0 || kb <= 1) return hipSuccess;
+    if (L >= 64) return launch_lu_u12_wide(L, bs, a, j0, kb, je, n, s);
     MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_u12<LL>), dim3((unsigned)(n - je)), dim3(64), 0, s, bs, a, j0, kb, je));
     return hipGetLastError();
 }
@@ -459,6 +462,10 @@ hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv,
     const dim3 g((unsigned)((nc + LASWP_CW - 1) / LASWP_CW), (unsigned)(L + 2));
     for (int64_t k = k0; k < k1; k += LASWP_MAXK) {
         const int64_t ke = k + LASWP_MAXK < k1 ? k + LASWP_MAXK : k1;
+        if (L >= 64) {   // the permutation moves words of every plane alike: any L
+            hipLaunchKernelGGL((k_lu_laswp<4>), g, dim3(LASWP_THREADS), 0, s, bs, a, piv, k, ke, c0, c1, c2, c3);
+            continue;
+        }
         MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_laswp<LL>), g, dim3(LASWP_THREADS), 0, s, bs, a, piv, k, ke, c0,
                                              c1, c2, c3));
     }
@@ -469,6 +476,7 @@ hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const in
                            hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
+    if (L >= 64) return launch_lu_solve_wide(L, bs, lu, x, piv, n, s);
     const dim3 g(1), b(SOLVE_REG_THREADS);
     if (n <= SOLVE_REG_THREADS) {
         MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 1>), g, b, 0, s, bs, lu, x, piv, n));

@@ -1,0 +1,549 @@
+// wide.hpp -- p-bit binary floating point held by a whole wavefront, for
+// p = 2048, 4096, 8192 (the paper's high precisions, Sections 3 and 4): the
+// same number format and rounding as mp_arith.hpp, one correctly rounded
+// result (to nearest, ties to even) per operation.
+//
+// A value is WMP<L> (L = 64 R limbs): lane t holds limbs R t .. R t + R - 1 of
+// the mantissa (limb 0 least significant, so lane 63 holds the top); the
+// exponent and sign are the same in every lane.  Every routine here must be
+// called by all 64 lanes of a wave with the same arguments' uniform parts:
+// lanes talk through ds_bpermute, readlane and ballots only (no LDS, no
+// memory), and every branch on data is on a wave-uniform value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mp_arith.hpp"
+
+namespace mpg {
+
+template <int L>
+struct WMP {
+    static constexpr int R = L / 64;
+    uint32_t m[L / 64];
+    int32_t e;
+    uint32_t s;
+};
+
+template <int L>
+constexpr bool is_wide() { return L >= 64; }
+
+__device__ __forceinline__ int wlane() { return (int)__lane_id(); }
+__device__ __forceinline__ uint64_t wballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+__device__ __forceinline__ uint32_t wuni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t wread(uint32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+// value v of lane src (src in [0, 63])
+__device__ __forceinline__ uint32_t wperm(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+__device__ __forceinline__ int top_bit64(uint64_t x) { return 63 - __builtin_clzll(x); }
+
+// register k (k the same in every lane) of an R-register set
+template <int R>
+__device__ __forceinline__ uint32_t pick(const uint32_t (&m)[R], int k)
+{
+    uint32_t v = m[0];
+#pragma unroll
+    for (int q = 1; q < R; q++) v = (k == q) ? m[q] : v;
+    return v;
+}
+
+template <int L>
+__device__ __forceinline__ WMP<L> wzero()
+{
+    WMP<L> r;
+#pragma unroll
+    for (int k = 0; k < L / 64; k++) r.m[k] = 0;
+    r.e = 0;
+    r.s = 0;
+    return r;
+}
+
+// limb g (g the same in every lane) as a wave-uniform value; 0 outside [0, L)
+template <int L>
+__device__ __forceinline__ uint32_t wlimb(const uint32_t (&m)[L / 64], int g)
+{
+    constexpr int R = L / 64;
+    if (g < 0 || g >= L) return 0u;
+    return wread(pick<R>(m, g % R), g / R);
+}
+
+// out[r] = limb R t + r + off of m in lane t (off the same in every lane),
+// 0 outside [0, L)
+template <int L>
+__device__ __forceinline__ void wshift_limbs(const uint32_t (&m)[L / 64], int off, uint32_t (&out)[L / 64])
+{
+    constexpr int R = L / 64;
+    const int t = wlane();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int g = R * t + r + off;
+        const int sr = (((r + off) % R) + R) % R;   // source register: the same in every lane
+        const int sl = (g - sr) / R;                  // source lane (exact division)
+        const uint32_t v = wperm(pick<R>(m, sr), sl & 63);
+        out[r] = (g >= 0 && g < L) ? v : 0u;
+    }
+}
+
+template <int L>
+__device__ __forceinline__ bool wis_zero(const WMP<L>& x)
+{
+    return wlimb<L>(x.m, L - 1) == 0u;
+}
+
+// x + y + cin over L limbs (cin 0 or 1, the same in every lane); returns the
+// carry out of the top limb.  Each lane adds its own limbs; the carries
+// between lanes come from one 64-bit addition of the lanes' generate and
+// propagate masks (carry into lane t = bit t of (G|P) + G + cin, xor G|P, xor G).
+template <int L>
+__device__ __forceinline__ uint32_t wadd(const uint32_t (&x)[L / 64], const uint32_t (&y)[L / 64], uint32_t cin,
+                                         uint32_t (&z)[L / 64])
+{
+    constexpr int R = L / 64;
+    uint32_t c = 0;
+    bool ones = true;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        z[r] = addc(x[r], y[r], c, &c);
+        ones = ones && (z[r] == 0xffffffffu);
+    }
+    const uint64_t G = wballot(c != 0), P = wballot(ones);
+    const uint64_t GP = G | P;
+    const uint64_t u = GP + G;
+    const uint64_t s = u + (uint64_t)cin;
+    const uint32_t cout = (u < GP || s < u) ? 1u : 0u;
+    uint32_t ci = (uint32_t)(((s ^ GP ^ G) >> wlane()) & 1u);
+#pragma unroll
+    for (int r = 0; r < R; r++) z[r] = addc(z[r], 0u, ci, &ci);
+    return cout;
+}
+
+// sign of M_a - M_b
+template <int L>
+__device__ __forceinline__ int wcmp_mant(const uint32_t (&a)[L / 64], const uint32_t (&b)[L / 64])
+{
+    constexpr int R = L / 64;
+    bool diff = false, gt = false;
+#pragma unroll
+    for (int r = R - 1; r >= 0; r--) {
+        if (!diff && a[r] != b[r]) {
+            diff = true;
+            gt = a[r] > b[r];
+        }
+    }
+    const uint64_t dm = wballot(diff);
+    if (dm == 0) return 0;
+    const int tl = top_bit64(dm);
+    return ((wballot(gt) >> tl) & 1u) ? 1 : -1;
+}
+
+// sign of |x| - |y|
+template <int L>
+__device__ __forceinline__ int cmp_abs(const WMP<L>& x, const WMP<L>& y)
+{
+    const bool zx = wis_zero<L>(x), zy = wis_zero<L>(y);
+    if (zx || zy) return zx ? (zy ? 0 : -1) : 1;
+    if (x.e != y.e) return x.e > y.e ? 1 : -1;
+    return wcmp_mant<L>(x.m, y.m);
+}
+
+// m := m + cu at limb 0 (cu 0 or 1); a carry out of the top (m was all ones)
+// leaves 2^(p-1) and adds one to e
+template <int L>
+__device__ __forceinline__ void wround_up(uint32_t (&m)[L / 64], uint32_t cu, int32_t& e)
+{
+    constexpr int R = L / 64;
+    if (!cu) return;
+    uint32_t zero[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) zero[r] = 0u;
+    if (wadd<L>(m, zero, 1u, m)) {
+        if (wlane() == 63) m[R - 1] = 0x80000000u;   // the other limbs wrapped to zero
+        e += 1;
+    }
+}
+
+// RN(x + y).  Y (the smaller magnitude) is aligned below X with a 64-bit
+// guard held as two wave-uniform words and every lower bit of Y folded into
+// the guard's lowest bit (a nonzero tail sits at least 62 bits below the
+// rounding position after the at most one-bit normalisation that can follow
+// an inexact alignment, so it only acts as the sticky bit); gaps of at most
+// one bit are exact.  A gap of p + 2 or more leaves X: |Y| < ulp(X) / 4.
+template <int L>
+__device__ __forceinline__ WMP<L> add_rn(const WMP<L>& x, const WMP<L>& y)
+{
+    constexpr int R = L / 64;
+    constexpr uint32_t p = 32u * L;
+    const int t = wlane();
+    const bool zx = wis_zero<L>(x), zy = wis_zero<L>(y);
+    if (zy) return zx ? wzero<L>() : x;
+    if (zx) return y;
+    const bool ygt = (y.e > x.e) || (y.e == x.e && wcmp_mant<L>(y.m, x.m) > 0);
+    WMP<L> X, Y;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        X.m[r] = ygt ? y.m[r] : x.m[r];
+        Y.m[r] = ygt ? x.m[r] : y.m[r];
+    }
+    X.e = ygt ? y.e : x.e;
+    Y.e = ygt ? x.e : y.e;
+    X.s = ygt ? y.s : x.s;
+    Y.s = ygt ? x.s : y.s;
+    const uint32_t d = (uint32_t)(X.e - Y.e);
+    if (d >= p + 2u) return X;
+    const bool subt = X.s != Y.s;
+    const int q = (int)(d >> 5);
+    const uint32_t sh = d & 31u;
+
+    // T = Y >> d: limb j = (Y[j+q+1] : Y[j+q]) >> sh
+    uint32_t y0[R], y1[R], T[R];
+    wshift_limbs<L>(Y.m, q, y0);
+    wshift_limbs<L>(Y.m, q + 1, y1);
+#pragma unroll
+    for (int r = 0; r < R; r++) T[r] = funnel(y1[r], y0[r], sh);
+    // guard limbs -1 and -2 of Y >> d, and the sticky OR of Y's bits below d - 64
+    const uint32_t yq = wlimb<L>(Y.m, q), yq1 = wlimb<L>(Y.m, q - 1), yq2 = wlimb<L>(Y.m, q - 2);
+    const uint32_t gh = funnel(yq, yq1, sh);
+    uint32_t gl = funnel(yq1, yq2, sh);
+    bool st = false;
+    if (d > 64u) {
+        const uint32_t s0 = d - 64u;
+        const int kq = (int)(s0 >> 5);
+        const uint32_t kb = s0 & 31u;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int g = R * t + r;
+            if (g < kq) st = st || (Y.m[r] != 0u);
+            else if (g == kq && kb) st = st || ((Y.m[r] & ((1u << kb) - 1u)) != 0u);
+        }
+    }
+    if (wballot(st) != 0) gl |= 1u;
+
+    uint32_t M[R];
+    uint32_t grh, grl, cout = 0;
+    if (!subt) {
+        cout = wadd<L>(X.m, T, 0u, M);
+        grh = gh;
+        grl = gl;
+    } else {
+        // X 2^64 - (T 2^64 + G): the guard part first, then X - T - borrow
+        const uint64_t G = ((uint64_t)gh << 32) | gl;
+        const uint64_t Gn = (uint64_t)0 - G;
+        grh = (uint32_t)(Gn >> 32);
+        grl = (uint32_t)Gn;
+        uint32_t Tn[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) Tn[r] = ~T[r];
+        wadd<L>(X.m, Tn, G != 0 ? 0u : 1u, M);
+    }
+    int32_t e = X.e;
+    if (cout) {
+        // (1 : M : guard) >> 1, the bit leaving the guard kept as sticky
+        uint32_t up[R];
+        wshift_limbs<L>(M, 1, up);
+        const uint32_t m0 = wlimb<L>(M, 0);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const uint32_t hi = (R * t + r == L - 1) ? 1u : up[r];
+            M[r] = funnel(hi, M[r], 1u);
+        }
+        const uint32_t lost = grl & 1u;
+        grl = funnel(grh, grl, 1u) | lost;
+        grh = funnel(m0, grh, 1u);
+        e += 1;
+    } else if (subt) {
+        // leading zeros of (M : guard); a shift of two or more bits only
+        // follows a gap of at most one bit, where nothing was dropped
+        bool nzl = false;
+        int topr = 0;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (M[r] != 0u) {
+                nzl = true;
+                topr = r;
+            }
+        const uint64_t nz = wballot(nzl);
+        uint32_t z;
+        if (nz != 0) {
+            const int tl = top_bit64(nz);
+            const int tr = (int)wread((uint32_t)topr, tl);
+            const uint32_t tv = wlimb<L>(M, R * tl + tr);
+            z = 32u * (uint32_t)(L - 1 - (R * tl + tr)) + (uint32_t)__builtin_clz(tv);
+        } else if (grh != 0u) {
+            z = 32u * L + (uint32_t)__builtin_clz(grh);
+        } else if (grl != 0u) {
+            z = 32u * L + 32u + (uint32_t)__builtin_clz(grl);
+        } else {
+            return wzero<L>();                      // exact cancellation: +0
+        }
+        if (z > 0) {
+            const int qz = (int)(z >> 5);
+            const uint32_t bz = z & 31u;
+            uint32_t a0[R], a1[R];
+            wshift_limbs<L>(M, -qz, a0);
+            wshift_limbs<L>(M, -qz - 1, a1);
+            // limbs below M are the guard (index -1, -2), then zeros
+            auto below = [&](int idx) -> uint32_t { return idx == -1 ? grh : (idx == -2 ? grl : 0u); };
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int ia = R * t + r - qz;
+                const uint32_t va = ia >= 0 ? a0[r] : below(ia);
+                const uint32_t vb = ia - 1 >= 0 ? a1[r] : below(ia - 1);
+                M[r] = bz ? funnel(va, vb, 32u - bz) : va;
+            }
+            const uint32_t h1 = below(-1 - qz), h2 = below(-2 - qz), h3 = below(-3 - qz);
+            const uint32_t ngh = bz ? funnel(h1, h2, 32u - bz) : h1;
+            const uint32_t ngl = bz ? funnel(h2, h3, 32u - bz) : h2;
+            grh = ngh;
+            grl = ngl;
+            e -= (int32_t)z;
+        }
+    }
+    // round to nearest even at the guard
+    const uint32_t rb = grh >> 31;
+    const bool sticky = ((grh & 0x7fffffffu) | grl) != 0u;
+    const uint32_t lsb = wlimb<L>(M, 0) & 1u;
+    wround_up<L>(M, rb & ((sticky ? 1u : 0u) | lsb), e);
+    WMP<L> res;
+#pragma unroll
+    for (int r = 0; r < R; r++) res.m[r] = M[r];
+    res.e = e;
+    res.s = X.s;
+    return res;
+}
+
+template <int L>
+__device__ __forceinline__ WMP<L> neg(const WMP<L>& x)
+{
+    WMP<L> r = x;
+    r.s = wis_zero<L>(x) ? 0u : (x.s ^ 1u);
+    return r;
+}
+
+template <int L>
+__device__ __forceinline__ WMP<L> sub_rn(const WMP<L>& x, const WMP<L>& y)
+{
+    return add_rn<L>(x, neg<L>(y));
+}
+
+// RN(a b).  Lane t forms the product columns 2R t .. 2R t + 2R - 1 (column c =
+// sum_i a_i b_(c-i), 96-bit accumulators): a_i is read from its lane as a
+// uniform value, the lane's b_(c-i) for its 2R columns is a window that slides
+// one limb per i (one ds_bpermute per i).  The columns are then carried into
+// 2L limbs (a lane's carry-out goes to the next lane, and the one-bit carries
+// that remain by the ballot lookahead), and the top p bits are rounded.
+template <int L>
+__device__ __forceinline__ WMP<L> mul_rn(const WMP<L>& a, const WMP<L>& b)
+{
+    constexpr int R = L / 64, R2 = 2 * L / 64;
+    const int t = wlane();
+    if (wis_zero<L>(a) || wis_zero<L>(b)) return wzero<L>();
+    const int c0 = R2 * t;
+    // limb g of b for this lane (g = c0 - i0 + v, the offset uniform)
+    auto bl = [&](int off) -> uint32_t {
+        const int g = c0 + off;
+        const int sr = ((off % R) + R) % R;
+        const uint32_t v = wperm(pick<R>(b.m, sr), ((g - sr) / R) & 63);
+        return (g >= 0 && g < L) ? v : 0u;
+    };
+    uint64_t acc[R2];
+    uint32_t c2[R2];
+#pragma unroll
+    for (int k = 0; k < R2; k++) {
+        acc[k] = 0;
+        c2[k] = 0;
+    }
+    // block of R2 steps i = i0 + u: column k takes b_(c0 + k - i0 - u) =
+    // bb[R2 + k - u], bb[m] = b_(c0 - i0 - R2 + m), m in [1, 2 R2)
+    uint32_t bb[2 * R2];
+#pragma unroll
+    for (int m = 0; m < 2 * R2; m++) bb[m] = bl(m - R2);
+    for (int i0 = 0; i0 < L; i0 += R2) {
+#pragma unroll
+        for (int u = 0; u < R2; u++) {
+            const uint32_t ai = wread(a.m[u % R], (i0 + u) / R);
+#pragma unroll
+            for (int k = 0; k < R2; k++) mac(acc[k], c2[k], ai, bb[R2 + k - u]);
+        }
+        // next block: bb'[R2 + m] = bb[m], bb'[m] = b_(c0 - i0 - 2 R2 + m)
+#pragma unroll
+        for (int m = 0; m < R2; m++) bb[R2 + m] = bb[m];
+#pragma unroll
+        for (int m = 0; m < R2; m++) bb[m] = bl(-i0 - 2 * R2 + m);
+    }
+    // columns -> limbs: this lane's 2R limbs and a carry-out below 2^43
+    uint32_t P[R2];
+    uint64_t cy = 0;
+#pragma unroll
+    for (int k = 0; k < R2; k++) {
+        const uint64_t lo = acc[k] + cy;
+        const uint32_t hi = c2[k] + (lo < cy ? 1u : 0u);
+        P[k] = (uint32_t)lo;
+        cy = (lo >> 32) | ((uint64_t)hi << 32);
+    }
+    const uint32_t inl = wperm((uint32_t)cy, (t - 1) & 63), inh = wperm((uint32_t)(cy >> 32), (t - 1) & 63);
+    uint64_t cin = t > 0 ? (((uint64_t)inh << 32) | inl) : 0u;
+    uint32_t c = 0;
+    P[0] = addc(P[0], (uint32_t)cin, 0u, &c);
+    P[1] = addc(P[1], (uint32_t)(cin >> 32), c, &c);
+    bool ones = (P[0] == 0xffffffffu) && (P[1] == 0xffffffffu);
+#pragma unroll
+    for (int k = 2; k < R2; k++) {
+        P[k] = addc(P[k], 0u, c, &c);
+        ones = ones && (P[k] == 0xffffffffu);
+    }
+    {
+        const uint64_t G = wballot(c != 0), Pm = wballot(ones);
+        const uint64_t GP = G | Pm;
+        uint32_t ci = (uint32_t)((((GP + G) ^ GP ^ G) >> t) & 1u);
+#pragma unroll
+        for (int k = 0; k < R2; k++) P[k] = addc(P[k], 0u, ci, &ci);
+    }
+    // product limb L + j for this lane's mantissa limbs j = R t + r: product
+    // lane 32 + t/2, register R (t mod 2) + r
+    uint32_t H[R];
+    const int sl = 32 + (t >> 1);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t ve = wperm(P[r], sl), vo = wperm(P[R + r], sl);
+        H[r] = (t & 1) ? vo : ve;
+    }
+    const uint32_t ptop = wread(P[R2 - 1], 63);
+    const uint32_t pl1 = wread(P[R2 - 1], 31);            // product limb L - 1
+    const bool n1 = (ptop >> 31) != 0;
+    bool lowl = false;                                     // product limbs 0 .. L - 2
+#pragma unroll
+    for (int k = 0; k < R2; k++)
+        if (c0 + k <= L - 2) lowl = lowl || (P[k] != 0u);
+    const bool low = wballot(lowl) != 0;
+    uint32_t M[R];
+    uint32_t rb, st;
+    if (n1) {
+#pragma unroll
+        for (int r = 0; r < R; r++) M[r] = H[r];
+        rb = pl1 >> 31;
+        st = (pl1 & 0x7fffffffu) != 0u || low;
+    } else {
+        uint32_t Hd[R];
+        wshift_limbs<L>(H, -1, Hd);
+#pragma unroll
+        for (int r = 0; r < R; r++) M[r] = funnel(H[r], (R * t + r == 0) ? pl1 : Hd[r], 31u);
+        rb = (pl1 >> 30) & 1u;
+        st = (pl1 & 0x3fffffffu) != 0u || low;
+    }
+    int32_t e = a.e + b.e - (n1 ? 0 : 1);
+    const uint32_t lsb = wlimb<L>(M, 0) & 1u;
+    wround_up<L>(M, rb & (st | lsb), e);
+    WMP<L> res;
+#pragma unroll
+    for (int r = 0; r < R; r++) res.m[r] = M[r];
+    res.e = e;
+    res.s = a.s ^ b.s;
+    return res;
+}
+
+// RN(x / y), y nonzero: restoring division of M_x 2^(p+1) by M_y, one
+// quotient bit per step (p + 2 bits), the remainder a sticky bit.  True
+// division, never a reciprocal.
+template <int L>
+__device__ __forceinline__ WMP<L> div_rn(const WMP<L>& x, const WMP<L>& y)
+{
+    constexpr int R = L / 64;
+    constexpr int p = 32 * L;
+    const int t = wlane();
+    if (wis_zero<L>(x)) return wzero<L>();
+    const bool ge = wcmp_mant<L>(x.m, y.m) >= 0;
+    uint32_t ny[R], Rr[R], Q[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        ny[r] = ~y.m[r];
+        Q[r] = 0u;
+    }
+    if (ge) wadd<L>(x.m, ny, 1u, Rr);           // M_x - M_y
+    else {
+#pragma unroll
+        for (int r = 0; r < R; r++) Rr[r] = x.m[r];
+    }
+    // quotient bit i (i = p .. 0) goes to mantissa bit i - off; bit off - 1 is
+    // the round bit, lower ones are sticky
+    const int off = ge ? 2 : 1;
+    uint32_t rbit = 0, sbit = 0;
+    for (int i = p; i >= 0; i--) {
+        // Rr := 2 Rr (the bit leaving the top kept in hb), then subtract M_y if it fits
+        uint32_t dn[R];
+        wshift_limbs<L>(Rr, -1, dn);
+        const uint32_t hb = wlimb<L>(Rr, L - 1) >> 31;
+#pragma unroll
+        for (int r = 0; r < R; r++) Rr[r] = funnel(Rr[r], dn[r], 31u);
+        uint32_t D[R];
+        const uint32_t nob = wadd<L>(Rr, ny, 1u, D);  // carry out: Rr >= M_y
+        const bool qb = hb != 0u || nob != 0u;
+        if (qb) {
+#pragma unroll
+            for (int r = 0; r < R; r++) Rr[r] = D[r];
+        }
+        if (qb) {
+            const int k = i - off;
+            if (k >= 0) {
+                const int kl = k >> 5;
+                if (t == kl / R) {
+#pragma unroll
+                    for (int r = 0; r < R; r++)
+                        if (r == kl % R) Q[r] |= 1u << (k & 31);
+                }
+            } else if (k == -1) {
+                rbit = 1u;
+            } else {
+                sbit = 1u;
+            }
+        }
+    }
+    // the leading quotient bit p + 1 (M_x >= M_y) is the mantissa's top bit
+    if (ge && t == 63) Q[R - 1] |= 0x80000000u;
+    bool rem = false;
+#pragma unroll
+    for (int r = 0; r < R; r++) rem = rem || (Rr[r] != 0u);
+    if (wballot(rem) != 0) sbit = 1u;
+    int32_t e = x.e - y.e + (ge ? 1 : 0);
+    const uint32_t lsb = wlimb<L>(Q, 0) & 1u;
+    wround_up<L>(Q, rbit & (sbit | lsb), e);
+    WMP<L> res;
+#pragma unroll
+    for (int r = 0; r < R; r++) res.m[r] = Q[r];
+    res.e = e;
+    res.s = x.s ^ y.s;
+    return res;
+}
+
+// ------------------------------------------------------------------ memory
+
+// element idx of a matrix in the plane layout: lane t loads limbs R t .. R t + R - 1
+template <int L>
+__device__ __forceinline__ WMP<L> wload(const uint32_t* __restrict__ base, int64_t ps, int64_t idx)
+{
+    constexpr int R = L / 64;
+    const int t = wlane();
+    WMP<L> x;
+#pragma unroll
+    for (int r = 0; r < R; r++) x.m[r] = base[(int64_t)(R * t + r) * ps + idx];
+    x.e = (int32_t)wuni(base[(int64_t)L * ps + idx]);
+    x.s = wuni(base[(int64_t)(L + 1) * ps + idx]);
+    return x;
+}
+
+template <int L>
+__device__ __forceinline__ void wstore(uint32_t* __restrict__ base, int64_t ps, int64_t idx, const WMP<L>& x)
+{
+    constexpr int R = L / 64;
+    const int t = wlane();
+#pragma unroll
+    for (int r = 0; r < R; r++) base[(int64_t)(R * t + r) * ps + idx] = x.m[r];
+    if (t == 0) {
+        base[(int64_t)L * ps + idx] = (uint32_t)x.e;
+        base[(int64_t)(L + 1) * ps + idx] = x.s;
+    }
+}
+
+}  // namespace mpg
