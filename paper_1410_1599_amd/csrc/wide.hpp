@@ -33,7 +33,9 @@ __device__ __forceinline__ int wlane() { return (int)__lane_id(); }
 __device__ __forceinline__ uint64_t wballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 __device__ __forceinline__ uint32_t wuni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint32_t wread(uint32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
-// value v of lane src (src in [0, 63])
+// value v of lane src (src in [0, 63]); every lane must be active (a
+// disabled source lane reads as 0), so it is never called under a condition
+// that differs between lanes
 __device__ __forceinline__ uint32_t wperm(uint32_t v, int src)
 {
     return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
@@ -444,74 +446,152 @@ __device__ __forceinline__ WMP<L> mul_rn(const WMP<L>& a, const WMP<L>& b)
     return res;
 }
 
-// RN(x / y), y nonzero: restoring division of M_x 2^(p+1) by M_y, one
-// quotient bit per step (p + 2 bits), the remainder a sticky bit.  True
-// division, never a reciprocal.
+// R := R - q M_y over the L lane-layout limbs of R and its top limb rh (q <
+// 2^32, the same in every lane); returns 1 if the result is negative (a
+// borrow out of rh).  Each lane runs its own multiply-subtract chain; what
+// it owes the next lane (the high product word and the borrow, at most 2^32)
+// is passed on by ds_bpermute and subtracted there, and the one-bit borrows
+// that remain travel by the ballot lookahead.
+template <int L>
+__device__ __forceinline__ uint32_t wsub_mul(uint32_t (&Rl)[L / 64], uint32_t& rh, uint32_t q,
+                                             const uint32_t (&v)[L / 64])
+{
+    constexpr int R = L / 64;
+    const int t = wlane();
+    uint32_t pc = 0, bw = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint64_t pr = (uint64_t)q * v[r] + pc;
+        pc = (uint32_t)(pr >> 32);
+        Rl[r] = subb(Rl[r], (uint32_t)pr, bw, &bw);
+    }
+    // permute with every lane active (an inactive source lane reads as 0),
+    // then drop lane 0's wrapped-around value
+    const uint32_t pp = wperm(pc, (t - 1) & 63), pb = wperm(bw, (t - 1) & 63);
+    const uint32_t in_pc = t > 0 ? pp : 0u;
+    const uint32_t in_bw = t > 0 ? pb : 0u;
+    uint32_t b = 0;
+    Rl[0] = subb(Rl[0], in_pc, in_bw, &b);
+    bool zeros = Rl[0] == 0u;
+#pragma unroll
+    for (int r = 1; r < R; r++) {
+        Rl[r] = subb(Rl[r], 0u, b, &b);
+        zeros = zeros && (Rl[r] == 0u);
+    }
+    const uint64_t G = wballot(b != 0), P = wballot(zeros);
+    const uint64_t GP = G | P;
+    const uint64_t u = GP + G;
+    const uint32_t top_b = u < GP ? 1u : 0u;
+    uint32_t bi = (uint32_t)(((u ^ GP ^ G) >> t) & 1u);
+#pragma unroll
+    for (int r = 0; r < R; r++) Rl[r] = subb(Rl[r], 0u, bi, &bi);
+    const uint32_t top_pc = wread(pc, 63), top_bw = wread(bw, 63);
+    uint32_t b1, b2;
+    rh = subb(rh, top_pc, top_bw, &b1);
+    rh = subb(rh, 0u, top_b, &b2);
+    return b1 | b2;
+}
+
+// RN(x / y), y nonzero: radix-2^32 long division (Knuth D) of
+// M_x 2^(32(L+1)) by M_y, the same steps and digit estimate as the one-lane
+// div_rn (mp_arith.hpp): the digit from the remainder's top three limbs and
+// M_y's top two in double precision is the true digit or one off either way,
+// corrected by adding M_y back or subtracting it once more.  The quotient
+// has p + 32 or p + 33 bits, so the round bit is exact and the rest plus the
+// remainder is the sticky bit.  True division, never a reciprocal multiply.
 template <int L>
 __device__ __forceinline__ WMP<L> div_rn(const WMP<L>& x, const WMP<L>& y)
 {
     constexpr int R = L / 64;
-    constexpr int p = 32 * L;
     const int t = wlane();
     if (wis_zero<L>(x)) return wzero<L>();
-    const bool ge = wcmp_mant<L>(x.m, y.m) >= 0;
-    uint32_t ny[R], Rr[R], Q[R];
+    const double D = (double)wlimb<L>(y.m, L - 1) * 4294967296.0 + (double)wlimb<L>(y.m, L - 2);
+    const double invD = 1.0 / D;
+    uint32_t Rl[R], Qw[R], nv[R];
+    uint32_t rh = 0, q_top = 0, q_last = 0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        ny[r] = ~y.m[r];
-        Q[r] = 0u;
+        Rl[r] = x.m[r];
+        Qw[r] = 0u;
+        nv[r] = ~y.m[r];
     }
-    if (ge) wadd<L>(x.m, ny, 1u, Rr);           // M_x - M_y
-    else {
+    for (int step = 0; step < L + 2; step++) {
+        const double N = ((double)rh * 4294967296.0 + (double)wlimb<L>(Rl, L - 1)) * 4294967296.0 +
+                         (double)wlimb<L>(Rl, L - 2);
+        double qd = floor(N * invD);
+        qd = qd > 4294967295.0 ? 4294967295.0 : qd;
+        uint32_t qh = wuni((uint32_t)qd);
+        uint32_t neg = wsub_mul<L>(Rl, rh, qh, y.m);
+        // negative: add M_y back (a carry out of the top limb ends it)
 #pragma unroll
-        for (int r = 0; r < R; r++) Rr[r] = x.m[r];
-    }
-    // quotient bit i (i = p .. 0) goes to mantissa bit i - off; bit off - 1 is
-    // the round bit, lower ones are sticky
-    const int off = ge ? 2 : 1;
-    uint32_t rbit = 0, sbit = 0;
-    for (int i = p; i >= 0; i--) {
-        // Rr := 2 Rr (the bit leaving the top kept in hb), then subtract M_y if it fits
-        uint32_t dn[R];
-        wshift_limbs<L>(Rr, -1, dn);
-        const uint32_t hb = wlimb<L>(Rr, L - 1) >> 31;
-#pragma unroll
-        for (int r = 0; r < R; r++) Rr[r] = funnel(Rr[r], dn[r], 31u);
-        uint32_t D[R];
-        const uint32_t nob = wadd<L>(Rr, ny, 1u, D);  // carry out: Rr >= M_y
-        const bool qb = hb != 0u || nob != 0u;
-        if (qb) {
-#pragma unroll
-            for (int r = 0; r < R; r++) Rr[r] = D[r];
-        }
-        if (qb) {
-            const int k = i - off;
-            if (k >= 0) {
-                const int kl = k >> 5;
-                if (t == kl / R) {
-#pragma unroll
-                    for (int r = 0; r < R; r++)
-                        if (r == kl % R) Q[r] |= 1u << (k & 31);
-                }
-            } else if (k == -1) {
-                rbit = 1u;
-            } else {
-                sbit = 1u;
+        for (int it = 0; it < 2; it++) {
+            if (neg) {
+                const uint32_t c = wadd<L>(Rl, y.m, 0u, Rl);
+                uint32_t c2;
+                rh = addc(rh, 0u, c, &c2);
+                qh -= 1;
+                neg = c2 ? 0u : 1u;
             }
         }
-    }
-    // the leading quotient bit p + 1 (M_x >= M_y) is the mantissa's top bit
-    if (ge && t == 63) Q[R - 1] |= 0x80000000u;
-    bool rem = false;
+        // still >= M_y: subtract once more (a second time only if the first went through)
 #pragma unroll
-    for (int r = 0; r < R; r++) rem = rem || (Rr[r] != 0u);
-    if (wballot(rem) != 0) sbit = 1u;
-    int32_t e = x.e - y.e + (ge ? 1 : 0);
-    const uint32_t lsb = wlimb<L>(Q, 0) & 1u;
-    wround_up<L>(Q, rbit & (sbit | lsb), e);
+        for (int it = 0; it < 2; it++) {
+            uint32_t T[R];
+            const uint32_t c = wadd<L>(Rl, nv, 1u, T);    // carry out: no borrow from the L limbs
+            uint32_t b2;
+            const uint32_t th = subb(rh, 0u, c ? 0u : 1u, &b2);
+            if (b2) break;
+#pragma unroll
+            for (int r = 0; r < R; r++) Rl[r] = T[r];
+            rh = th;
+            qh += 1;
+        }
+        // digit `step` is quotient limb L + 1 - step: the top one, the L
+        // mantissa-window limbs (lane layout), the last one
+        if (step == 0) {
+            q_top = qh;
+        } else if (step <= L) {
+            const int k = L - step;
+            if (t == k / R) {
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    if (r == k % R) Qw[r] = qh;
+            }
+        } else {
+            q_last = qh;
+        }
+        // next window: the remainder (now < M_y) times 2^32
+        rh = wlimb<L>(Rl, L - 1);
+        uint32_t sh[R];
+        wshift_limbs<L>(Rl, -1, sh);
+#pragma unroll
+        for (int r = 0; r < R; r++) Rl[r] = sh[r];
+    }
+    bool reml = false;
+#pragma unroll
+    for (int r = 0; r < R; r++) reml = reml || (Rl[r] != 0u);
+    const bool rem = wballot(reml) != 0 || rh != 0u;
+    const bool big = q_top != 0u;                 // M_x >= M_y: p + 33 bits
+    uint32_t M[R], rb, st;
+    if (big) {
+        uint32_t up[R];
+        wshift_limbs<L>(Qw, 1, up);
+#pragma unroll
+        for (int r = 0; r < R; r++) M[r] = funnel((R * t + r == L - 1) ? q_top : up[r], Qw[r], 1u);
+        rb = wlimb<L>(Qw, 0) & 1u;
+        st = (q_last != 0u || rem) ? 1u : 0u;
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) M[r] = Qw[r];
+        rb = q_last >> 31;
+        st = ((q_last & 0x7fffffffu) != 0u || rem) ? 1u : 0u;
+    }
+    int32_t e = x.e - y.e + (big ? 1 : 0);
+    const uint32_t lsb = wlimb<L>(M, 0) & 1u;
+    wround_up<L>(M, rb & (st | lsb), e);
     WMP<L> res;
 #pragma unroll
-    for (int r = 0; r < R; r++) res.m[r] = Q[r];
+    for (int r = 0; r < R; r++) res.m[r] = M[r];
     res.e = e;
     res.s = x.s ^ y.s;
     return res;

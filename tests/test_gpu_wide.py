@@ -44,18 +44,6 @@ def test_wide_scalar_ops(p):
     for name, fn, ref in (("mul", mp.mp_mul_ew, mpnum.mul), ("add", mp.mp_add, mpnum.add),
                           ("sub", mp.mp_sub, mpnum.sub), ("div", mp.mp_div_ew, mpnum.div)):
         keep = [k for k, (_, y) in enumerate(pairs) if y[0] != 0] if name == "div" else range(N)
-        if name == "div":
-            keep = keep[::7]                  # bit-serial division: a sample of the pairs
-            Xs = vec_planes([pairs[k][0] for k in keep], p)
-            Ys = vec_planes([pairs[k][1] for k in keep], p)
-            dZ = mp.empty(1, len(keep), p)
-            fn(1, len(keep), p, mp.to_device(Xs), mp.to_device(Ys), dZ)
-            sync()
-            Z = mp.to_host(dZ)
-            for q, k in enumerate(keep):
-                x, y = pairs[k]
-                assert I.entry(Z, 0, q, p) == ref(x, y, p), (name, p, x, y)
-            continue
         dZ = mp.empty(1, N, p)
         fn(1, N, p, dX, dY, dZ)
         sync()
@@ -63,6 +51,31 @@ def test_wide_scalar_ops(p):
         for k in keep:
             x, y = pairs[k]
             assert I.entry(Z, 0, k, p) == ref(x, y, p), (name, p, x, y)
+
+
+@pytest.mark.parametrize("p", WIDE)
+def test_wide_division_digit_estimate(p):
+    """Divisors with long runs of ones or zeros below the top limbs, and
+    quotients near 1, stress the radix-2^32 digit estimate and its corrections."""
+    rng = random.Random(950 + p)
+    one = 1 << (p - 1)
+    pairs = [(random_value(rng, p, -300, 300), random_value(rng, p, -300, 300)) for _ in range(300)]
+    for _ in range(150):
+        run = rng.randrange(1, p)
+        pairs.append(((rng.randrange(one, 1 << p), 0), (((1 << p) - 1) ^ ((1 << run) - 1) | one, 0)))
+        pairs.append(((rng.randrange(one, 1 << p), 0), (one | ((1 << run) - 1), 0)))
+        pairs.append((((1 << p) - 1 - rng.randrange(0, 1 << 16), 0), (one + rng.randrange(0, 1 << 16), 0)))
+        m = rng.randrange(one, 1 << p)
+        pairs.append(((m, 3), (m, 1)))
+        pairs.append(((m, 0), (m + 1 if m + 1 < (1 << p) else m - 1, 0)))
+    X = vec_planes([x for x, _ in pairs], p)
+    Y = vec_planes([y for _, y in pairs], p)
+    dZ = mp.empty(1, len(pairs), p)
+    mp.mp_div_ew(1, len(pairs), p, mp.to_device(X), mp.to_device(Y), dZ)
+    sync()
+    Z = mp.to_host(dZ)
+    for k, (x, y) in enumerate(pairs):
+        assert I.entry(Z, 0, k, p) == mpnum.div(x, y, p), (x, y)
 
 
 @pytest.mark.parametrize("p", WIDE)
