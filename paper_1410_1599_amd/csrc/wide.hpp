@@ -330,108 +330,172 @@ __device__ __forceinline__ WMP<L> sub_rn(const WMP<L>& x, const WMP<L>& y)
     return add_rn<L>(x, neg<L>(y));
 }
 
-// RN(a b).  Lane t forms the product columns 2R t .. 2R t + 2R - 1 (column c =
-// sum_i a_i b_(c-i), 96-bit accumulators): a_i is read from its lane as a
-// uniform value, the lane's b_(c-i) for its 2R columns is a window that slides
-// one limb per i (one ds_bpermute per i).  The columns are then carried into
-// 2L limbs (a lane's carry-out goes to the next lane, and the one-bit carries
-// that remain by the ballot lookahead), and the top p bits are rounded.
+// RN(a b).  Lane t forms the low product columns R t + k and the high ones
+// L + R t + k (k < R), column c = sum_i a_i b_(c-i) in 96-bit accumulators.
+// At step s column k of the lane takes a_(s+k) (a wave-uniform value, read
+// from its lane) times b_((R t - s) mod L), the same b limb for all k (one
+// ds_bpermute per step): for s <= R t that is a term of the low column, for
+// s > R t of the high one, so every lane does exactly L R limb products and
+// switches its accumulators once, at s = R t + 1, which is a block boundary
+// of the R-step blocks below.  The columns are then carried into 2L limbs (a
+// lane's carry-out goes to the next lane of its half, the low half's last lane
+// feeds the high half's first, and the one-bit carries that remain travel by
+// a 128-lane ballot lookahead): the high half is already the mantissa's lane
+// layout, and its top p bits are rounded.
 template <int L>
 __device__ __forceinline__ WMP<L> mul_rn(const WMP<L>& a, const WMP<L>& b)
 {
-    constexpr int R = L / 64, R2 = 2 * L / 64;
+    constexpr int R = L / 64;
+    constexpr int NB = (L + R - 1 + R - 1) / R;       // blocks covering s = 1 - R .. L - 1
     const int t = wlane();
     if (wis_zero<L>(a) || wis_zero<L>(b)) return wzero<L>();
-    const int c0 = R2 * t;
-    // limb g of b for this lane (g = c0 - i0 + v, the offset uniform)
-    auto bl = [&](int off) -> uint32_t {
-        const int g = c0 + off;
-        const int sr = ((off % R) + R) % R;
-        const uint32_t v = wperm(pick<R>(b.m, sr), ((g - sr) / R) & 63);
-        return (g >= 0 && g < L) ? v : 0u;
-    };
-    uint64_t acc[R2];
-    uint32_t c2[R2];
+    uint64_t acc[R], accl[R];
+    uint32_t c2[R], c2l[R];
 #pragma unroll
-    for (int k = 0; k < R2; k++) {
+    for (int k = 0; k < R; k++) {
         acc[k] = 0;
         c2[k] = 0;
+        accl[k] = 0;
+        c2l[k] = 0;
     }
-    // block of R2 steps i = i0 + u: column k takes b_(c0 + k - i0 - u) =
-    // bb[R2 + k - u], bb[m] = b_(c0 - i0 - R2 + m), m in [1, 2 R2)
-    uint32_t bb[2 * R2];
+    uint32_t bnext[R];
 #pragma unroll
-    for (int m = 0; m < 2 * R2; m++) bb[m] = bl(m - R2);
-    for (int i0 = 0; i0 < L; i0 += R2) {
+    for (int u = 0; u < R; u++) bnext[u] = wperm(b.m[R - 1 - u], t & 63);
+    for (int q = 0; q < NB; q++) {
+        // block q: s = R (q - 1) + 1 + u, u < R; lane q - 1 leaves its low columns
+        if (t == q - 1) {
 #pragma unroll
-        for (int u = 0; u < R2; u++) {
-            const uint32_t ai = wread(a.m[u % R], (i0 + u) / R);
-#pragma unroll
-            for (int k = 0; k < R2; k++) mac(acc[k], c2[k], ai, bb[R2 + k - u]);
+            for (int k = 0; k < R; k++) {
+                accl[k] = acc[k];
+                c2l[k] = c2[k];
+                acc[k] = 0;
+                c2[k] = 0;
+            }
         }
-        // next block: bb'[R2 + m] = bb[m], bb'[m] = b_(c0 - i0 - 2 R2 + m)
+        // a_(s+k) for this block: limbs R (q - 1) + 1 + v, v < 2R - 1
+        uint32_t aw[2 * R - 1];
 #pragma unroll
-        for (int m = 0; m < R2; m++) bb[R2 + m] = bb[m];
+        for (int v = 0; v < 2 * R - 1; v++) {
+            const int g = R * (q - 1) + 1 + v;
+            const uint32_t x = wread(a.m[(1 + v) % R], (q - 1 + (1 + v) / R) & 63);
+            aw[v] = (g >= 0 && g < L) ? x : 0u;
+        }
+        // b_((R t - s) mod L) = limb R ((t - q) mod 64) + R - 1 - u, fetched
+        // one block ahead so the permute latency hides under the products
+        uint32_t bw[R];
 #pragma unroll
-        for (int m = 0; m < R2; m++) bb[m] = bl(-i0 - 2 * R2 + m);
+        for (int u = 0; u < R; u++) bw[u] = bnext[u];
+        {
+            const int src = (t - q - 1) & 63;
+#pragma unroll
+            for (int u = 0; u < R; u++) bnext[u] = wperm(b.m[R - 1 - u], src);
+        }
+#pragma unroll
+        for (int u = 0; u < R; u++) {
+            uint64_t cy[R];
+#pragma unroll
+            for (int k = 0; k < R; k++)
+                asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc[k]), "=s"(cy[k]) : "v"(aw[u + k]), "v"(bw[u]));
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                uint64_t unused;
+                asm volatile("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(c2[k]), "=s"(unused) : "s"(cy[k]));
+            }
+        }
     }
-    // columns -> limbs: this lane's 2R limbs and a carry-out below 2^43
-    uint32_t P[R2];
-    uint64_t cy = 0;
+    if (t >= NB - 1) {                                 // lanes whose switch lies past the last block
 #pragma unroll
-    for (int k = 0; k < R2; k++) {
-        const uint64_t lo = acc[k] + cy;
-        const uint32_t hi = c2[k] + (lo < cy ? 1u : 0u);
-        P[k] = (uint32_t)lo;
-        cy = (lo >> 32) | ((uint64_t)hi << 32);
+        for (int k = 0; k < R; k++) {
+            accl[k] = acc[k];
+            c2l[k] = c2[k];
+            acc[k] = 0;
+            c2[k] = 0;
+        }
     }
-    const uint32_t inl = wperm((uint32_t)cy, (t - 1) & 63), inh = wperm((uint32_t)(cy >> 32), (t - 1) & 63);
-    uint64_t cin = t > 0 ? (((uint64_t)inh << 32) | inl) : 0u;
-    uint32_t c = 0;
-    P[0] = addc(P[0], (uint32_t)cin, 0u, &c);
-    P[1] = addc(P[1], (uint32_t)(cin >> 32), c, &c);
-    bool ones = (P[0] == 0xffffffffu) && (P[1] == 0xffffffffu);
+    // columns -> limbs, low half PL and high half PH, and each lane's carry-out (< 2^43)
+    uint32_t PL[R], PH[R];
+    uint64_t cyl = 0, cyh = 0;
 #pragma unroll
-    for (int k = 2; k < R2; k++) {
-        P[k] = addc(P[k], 0u, c, &c);
-        ones = ones && (P[k] == 0xffffffffu);
+    for (int k = 0; k < R; k++) {
+        uint64_t lo = accl[k] + cyl;
+        uint32_t hi = c2l[k] + (lo < cyl ? 1u : 0u);
+        PL[k] = (uint32_t)lo;
+        cyl = (lo >> 32) | ((uint64_t)hi << 32);
+        lo = acc[k] + cyh;
+        hi = c2[k] + (lo < cyh ? 1u : 0u);
+        PH[k] = (uint32_t)lo;
+        cyh = (lo >> 32) | ((uint64_t)hi << 32);
+    }
+    const int prev = (t - 1) & 63;
+    const uint32_t l0 = wperm((uint32_t)cyl, prev), l1 = wperm((uint32_t)(cyl >> 32), prev);
+    const uint32_t h0 = wperm((uint32_t)cyh, prev), h1 = wperm((uint32_t)(cyh >> 32), prev);
+    const uint64_t inl = t > 0 ? (((uint64_t)l1 << 32) | l0) : 0u;
+    const uint64_t inh = t > 0 ? (((uint64_t)h1 << 32) | h0) : (((uint64_t)l1 << 32) | l0);   // lane 0: low lane 63
+    uint32_t gl = 0, gh = 0;
+    bool onesl = true, onesh = true;
+    if constexpr (R == 1) {
+        // one limb per lane: the incoming carry (< 2^43) leaves up to 2^11
+        // over, which goes one lane further before only one-bit carries remain
+        const uint64_t vl = (uint64_t)PL[0] + inl, vh = (uint64_t)PH[0] + inh;
+        PL[0] = (uint32_t)vl;
+        PH[0] = (uint32_t)vh;
+        const uint32_t ol = (uint32_t)(vl >> 32), oh = (uint32_t)(vh >> 32);
+        const uint32_t pol = wperm(ol, prev), poh = wperm(oh, prev);
+        const uint32_t il = t > 0 ? pol : 0u, ih = t > 0 ? poh : pol;
+        PL[0] = addc(PL[0], il, 0u, &gl);
+        PH[0] = addc(PH[0], ih, 0u, &gh);
+        onesl = PL[0] == 0xffffffffu;
+        onesh = PH[0] == 0xffffffffu;
+    } else {
+        PL[0] = addc(PL[0], (uint32_t)inl, 0u, &gl);
+        PH[0] = addc(PH[0], (uint32_t)inh, 0u, &gh);
+        PL[1] = addc(PL[1], (uint32_t)(inl >> 32), gl, &gl);
+        PH[1] = addc(PH[1], (uint32_t)(inh >> 32), gh, &gh);
+#pragma unroll
+        for (int k = 2; k < R; k++) {
+            PL[k] = addc(PL[k], 0u, gl, &gl);
+            PH[k] = addc(PH[k], 0u, gh, &gh);
+        }
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            onesl = onesl && (PL[k] == 0xffffffffu);
+            onesh = onesh && (PH[k] == 0xffffffffu);
+        }
     }
     {
-        const uint64_t G = wballot(c != 0), Pm = wballot(ones);
-        const uint64_t GP = G | Pm;
-        uint32_t ci = (uint32_t)((((GP + G) ^ GP ^ G) >> t) & 1u);
+        // 128-lane lookahead: low lanes then high lanes
+        const uint64_t Gl = wballot(gl != 0), Pl = wballot(onesl), Gh = wballot(gh != 0), Ph = wballot(onesh);
+        const uint64_t GPl = Gl | Pl, GPh = Gh | Ph;
+        const uint64_t lo = GPl + Gl;
+        const uint64_t hi = GPh + Gh + (lo < GPl ? 1u : 0u);
+        uint32_t cl = (uint32_t)(((lo ^ GPl ^ Gl) >> t) & 1u);
+        uint32_t ch = (uint32_t)(((hi ^ GPh ^ Gh) >> t) & 1u);
 #pragma unroll
-        for (int k = 0; k < R2; k++) P[k] = addc(P[k], 0u, ci, &ci);
+        for (int k = 0; k < R; k++) {
+            PL[k] = addc(PL[k], 0u, cl, &cl);
+            PH[k] = addc(PH[k], 0u, ch, &ch);
+        }
     }
-    // product limb L + j for this lane's mantissa limbs j = R t + r: product
-    // lane 32 + t/2, register R (t mod 2) + r
-    uint32_t H[R];
-    const int sl = 32 + (t >> 1);
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const uint32_t ve = wperm(P[r], sl), vo = wperm(P[R + r], sl);
-        H[r] = (t & 1) ? vo : ve;
-    }
-    const uint32_t ptop = wread(P[R2 - 1], 63);
-    const uint32_t pl1 = wread(P[R2 - 1], 31);            // product limb L - 1
+    const uint32_t ptop = wread(PH[R - 1], 63);
+    const uint32_t pl1 = wread(PL[R - 1], 63);           // product limb L - 1
     const bool n1 = (ptop >> 31) != 0;
     bool lowl = false;                                     // product limbs 0 .. L - 2
 #pragma unroll
-    for (int k = 0; k < R2; k++)
-        if (c0 + k <= L - 2) lowl = lowl || (P[k] != 0u);
+    for (int k = 0; k < R; k++)
+        if (R * t + k <= L - 2) lowl = lowl || (PL[k] != 0u);
     const bool low = wballot(lowl) != 0;
     uint32_t M[R];
     uint32_t rb, st;
     if (n1) {
 #pragma unroll
-        for (int r = 0; r < R; r++) M[r] = H[r];
+        for (int r = 0; r < R; r++) M[r] = PH[r];
         rb = pl1 >> 31;
         st = (pl1 & 0x7fffffffu) != 0u || low;
     } else {
         uint32_t Hd[R];
-        wshift_limbs<L>(H, -1, Hd);
+        wshift_limbs<L>(PH, -1, Hd);
 #pragma unroll
-        for (int r = 0; r < R; r++) M[r] = funnel(H[r], (R * t + r == 0) ? pl1 : Hd[r], 31u);
+        for (int r = 0; r < R; r++) M[r] = funnel(PH[r], (R * t + r == 0) ? pl1 : Hd[r], 31u);
         rb = (pl1 >> 30) & 1u;
         st = (pl1 & 0x3fffffffu) != 0u || low;
     }

@@ -4,6 +4,8 @@
 // (gemm_kernels.hip, lu_kernels.hip), so the results are the same correctly
 // rounded sequence the CPU oracle forms; a workgroup of four waves walks the
 // same tiles, each wave taking every fourth element of a tile.
+#include <algorithm>
+
 #include "launch.hpp"
 #include "node_ops.hpp"
 #include "wide.hpp"
@@ -14,6 +16,10 @@ namespace {
 
 constexpr int WT = 256;                // threads per workgroup: four waves
 constexpr int WW = WT / 64;
+// A tile (256 elements of a leaf product or node pass) is split over SPLIT
+// workgroups, so every element gets its own wave: enough waves per SIMD to
+// hide the latency of the long dependent carry chains of one value.
+constexpr int SPLIT = 16, PER = 256 / SPLIT;
 
 template <int L>
 __device__ __forceinline__ WMP<L> wld(const Bases& bs, const MatRef& r, int64_t i, int64_t j)
@@ -40,13 +46,16 @@ __global__ void __launch_bounds__(WT)
 k_gemm_w(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
 {
     const int w = wave_id();
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    static_assert(64 * GEMM_TM == 256, "a leaf tile holds 256 elements");
+    for (int64_t vb = blockIdx.x; vb < ntiles * SPLIT; vb += gridDim.x) {
+        const int64_t t = vb / SPLIT;
+        const int part = (int)(vb % SPLIT);
         const GemmTask T = tasks[tile_task[t]];
         const int64_t lt = t - T.tile0;
         const int tc = 1 << T.tcl;
         const int tr = (64 * GEMM_TM) >> T.tcl;
         const int tn = (T.n + tc - 1) >> T.tcl;
-        for (int el = w; el < 64 * GEMM_TM; el += WW) {
+        for (int el = part * PER + w; el < (part + 1) * PER; el += WW) {
             const int64_t i = (lt / tn) * tr + (el >> T.tcl);
             const int64_t j = (lt % tn) * tc + (el & (tc - 1));
             if (i >= T.m || j >= T.n) continue;
@@ -64,10 +73,13 @@ __global__ void __launch_bounds__(WT)
 k_node_w(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
 {
     const int w = wave_id();
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    static_assert(NODE_TILE == 256, "a node tile holds 256 elements");
+    for (int64_t vb = blockIdx.x; vb < ntiles * SPLIT; vb += gridDim.x) {
+        const int64_t t = vb / SPLIT;
+        const int part = (int)(vb % SPLIT);
         const NodeTask& T = tasks[tile_task[t]];
         const int64_t total = (int64_t)T.rows * T.cols;
-        for (int el = w; el < NODE_TILE; el += WW) {
+        for (int el = part * PER + w; el < (part + 1) * PER; el += WW) {
             const int64_t e = (t - T.tile0) * NODE_TILE + el;
             if (e >= total) break;
             node_apply<WMP<L>, L, OP>(bs, T, e / T.cols, e % T.cols);
@@ -239,7 +251,8 @@ hipError_t launch_gemm_wide(int L, const GemmTask* tasks, const int32_t* tile_ta
                             int64_t grid, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_gemm_w<LL>), dim3((unsigned)grid), dim3(WT), 0, s, tasks, tile_task,
+    const int64_t g = std::min<int64_t>(grid * SPLIT, int64_t(1) << 30);
+    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_gemm_w<LL>), dim3((unsigned)g), dim3(WT), 0, s, tasks, tile_task,
                                             ntiles, bs));
     return hipGetLastError();
 }
@@ -271,10 +284,11 @@ hipError_t launch_node_wide(int L, int op, const NodeTask* tasks, const int32_t*
                             const Bases& bs, int64_t grid, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(grid * SPLIT, int64_t(1) << 30);
     switch (L) {
-    case 64: return node_wide_L<64>(op, tasks, tile_task, ntiles, bs, grid, s);
-    case 128: return node_wide_L<128>(op, tasks, tile_task, ntiles, bs, grid, s);
-    case 256: return node_wide_L<256>(op, tasks, tile_task, ntiles, bs, grid, s);
+    case 64: return node_wide_L<64>(op, tasks, tile_task, ntiles, bs, g, s);
+    case 128: return node_wide_L<128>(op, tasks, tile_task, ntiles, bs, g, s);
+    case 256: return node_wide_L<256>(op, tasks, tile_task, ntiles, bs, g, s);
     default: return hipErrorInvalidValue;
     }
 }
