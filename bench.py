@@ -17,6 +17,7 @@ timed on a bounded sample of the same product.
 
 import argparse
 import json
+import math
 from fractions import Fraction
 import os
 import sys
@@ -58,6 +59,14 @@ def profiled_traffic(path):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def log10_fraction(q):
+    """log10 of a positive Fraction far outside the double range."""
+    def l10(v):
+        sh = max(0, v.bit_length() - 64)
+        return math.log10(v >> sh) + sh * math.log10(2.0)
+    return l10(q.numerator) - l10(q.denominator)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,11 +86,15 @@ def parse():
                     help="the paper's LU experiment (Section 4): no pivoting, n=1024, panel K = 32..320 with Winograd "
                          "trailing updates (cutoff 32) against column-wise LU (one panel), random at 256 bits and "
                          "Lotkin at 512 bits, x = [0..n-1]; 0: skip")
+    ap.add_argument("--lotkin-8192", type=int, default=512,
+                    help="the paper's 8192-bit Lotkin LU (Section 4) at this n (the paper: 1024; 0: skip): no "
+                         "pivoting, Winograd trailing updates (cutoff 32) with K = 32, 64, 128 against column-wise LU, "
+                         "x = [0..n-1]; times and the solution's relative error in decimal digits")
     ap.add_argument("--paper-grid", type=int, default=1,
                     help="the paper's own matrices (Section 3: a_ij = sqrt5 (i+j-1), b_ij = sqrt3 (n-i+1)), cutoff 32, "
                          "mixed odd-size policy: square n = 255..2049 and Table 5's m = n = 1024 with l = 63..513 at "
-                         "128 bits, square n = 255..2048 at 1024 bits; times and sampled relative errors against the "
-                         "closed form; 0: skip")
+                         "128 bits, square n = 255..2048 at 1024 bits and 255..512 at 8192 bits; times and sampled "
+                         "relative errors against the closed form; 0: skip")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving run (0: skip): Poisson arrivals at 0.8 x the measured "
                          "saturated rate, 90%% products / 10%% LU solves, 128/256/512 bits")
@@ -328,6 +341,40 @@ def main():
                               "max_abs_x_minus_xtrue": float(err)}
             del dAl, work, db, dx
 
+    lotkin_8192 = None
+    if args.lotkin_8192:
+        pw, nw = 8192, args.lotkin_8192
+        Ah = I.lotkin(nw, pw)
+        dAw = mp.to_device(Ah)
+        dbw = mp.empty(nw, 1, pw)
+        mp.mp_gemm(nw, nw, 1, pw, mp.SIMPLE, 0, dAw, mp.to_device(I.arange_column(nw, pw)), dbw)
+        work = dAw.clone()
+        piv = torch.zeros(nw, dtype=torch.int32, device="cuda")
+        times, digits = {}, {}
+        for K in (32, 64, 128, nw):
+            for _ in range(2):
+                work.copy_(dAw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = mp.mp_lu_nopivot(nw, pw, work, piv, K, mp.WINOGRAD, 32)
+                torch.cuda.synchronize()
+                tk = time.perf_counter() - t0
+            name = "column-wise" if K == nw else "K=%d" % K
+            times[name] = round(tk * 1e3, 1)
+            dx = dbw.clone()
+            mp.mp_lu_solve(nw, pw, work, piv, dx)
+            xh = mp.to_host(dx)
+            worst = max(abs(Fraction(sig) * Fraction(2) ** (e - pw) - i) / i
+                        for i, (sig, e) in ((i, I.entry(xh, i, 0, pw)) for i in range(1, nw)))
+            digits[name] = round(-log10_fraction(worst), 1) if worst > 0 else None
+        bestK = min((k for k in times if k != "column-wise"), key=lambda k: times[k])
+        lotkin_8192 = {"n": nw, "prec": pw, "info": info, "lu_ms": times, "best": bestK,
+                       "time_saved_vs_columnwise": round(1 - times[bestK] / times["column-wise"], 4),
+                       "correct_decimal_digits_of_x": digits,
+                       "config": "Lotkin matrix, no pivoting, Winograd trailing updates with cutoff 32, b = A x with "
+                                 "x = [0..n-1] by Simple at 8192 bits; times are the second of two runs"}
+        del dAw, work, dbw
+
     paper_grid = None
     if args.paper_grid:
         from math import isqrt
@@ -335,14 +382,14 @@ def main():
         def rel_err(C, m, l, n, pg):
             # rows 0, m/2, m-1, every column; exact c_ij = sqrt15 R_i, sqrt15 R_i to 3p fraction bits
             tail = sum(k * (n - k + 1) for k in range(1, l + 1))
-            worst = 0.0
+            worst = Fraction(0)
             for i in sorted({0, m // 2, m - 1}):
                 R = i * l * (2 * n - l + 1) // 2 + tail
                 K = 3 * pg
                 X = Fraction(isqrt(15 * R * R << (2 * K)), 1 << K)
                 for j in range(n):
                     sig, e = I.entry(C, i, j, pg)
-                    worst = max(worst, float(abs(Fraction(sig) * Fraction(2) ** (e - pg) - X) / X))
+                    worst = max(worst, abs(Fraction(sig) * Fraction(2) ** (e - pg) - X) / X)
             return worst
 
         def run(m, l, n, algos, pg=128):
@@ -357,12 +404,14 @@ def main():
                     mp.mp_gemm_ex(m, l, n, pg, al, 32, mp.MIXED, mp.LEAF_SIMPLE, dA8, dB8, dC8)
                     torch.cuda.synchronize()
                     tk = time.perf_counter() - t0
+                worst = rel_err(mp.to_host(dC8), m, l, n, pg)
                 out[name] = {"ms": round(tk * 1e3, 3), "2mln_per_s": 2.0 * m * l * n / tk,
-                             "max_rel_err_sampled": rel_err(mp.to_host(dC8), m, l, n, pg)}
+                             "max_rel_err_sampled": float(worst),
+                             "max_rel_err_sampled_log10": round(log10_fraction(worst), 2) if worst else None}
             return out
 
         paper_grid = {"config": "cutoff 32, mixed policy; relative errors on rows 0, m/2, m-1",
-                      "square": {}, "table5_m_n_1024": {}, "square_1024bit": {}}
+                      "square": {}, "table5_m_n_1024": {}, "square_1024bit": {}, "square_8192bit": {}}
         for nn in (255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049):
             paper_grid["square"][nn] = run(nn, nn, nn, ("simple", "block", "strassen", "winograd"))
         for ll in (63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513):
@@ -370,6 +419,9 @@ def main():
         for nn in (255, 256, 511, 512, 1023, 1024, 2048):
             paper_grid["square_1024bit"][nn] = run(nn, nn, nn, ("simple", "block", "strassen", "winograd")
                                                    if nn <= 1024 else ("strassen", "winograd"), pg=1024)
+        for nn in (255, 256, 511, 512):
+            paper_grid["square_8192bit"][nn] = run(nn, nn, nn, ("simple", "block", "strassen", "winograd")
+                                                   if nn <= 256 else ("strassen", "winograd"), pg=8192)
 
     serve_res = None
     if args.serve_requests > 0:
@@ -416,7 +468,7 @@ def main():
                                "seeds 6/7" % (n, p, args.algo, args.cutoff),
                    "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others, "slice": slice_res,
-        "accuracy": accuracy, "serve": serve_res, "lu": lu_res, "lu_paper": lu_paper, "paper_grid": paper_grid,
+        "accuracy": accuracy, "serve": serve_res, "lu": lu_res, "lu_paper": lu_paper, "lotkin_8192": lotkin_8192, "paper_grid": paper_grid,
     }
     print(json.dumps(out))
 

@@ -14,7 +14,10 @@
  * algorithms (here with partial pivoting).
  *
  * ------------------------------------------------------------------ numbers
- * prec p is 128, 256, 512 or 1024 bits; L = p / 32.  A value is
+ * prec p is 128, 256, 512, 1024, 2048, 4096 or 8192 bits (Section 3 uses
+ * 128 to 8192); L = p / 32.  Up to 1024 bits a GPU lane holds one value; from
+ * 2048 bits a whole wavefront does (its 64 lanes each hold L / 64 limbs), with
+ * the same results.  A value is
  *     (-1)^s * M * 2^(e - p),   2^(p-1) <= M < 2^p   (M normalised),
  * or zero (M = 0, e = 0, s = 0; there is one zero, +0).  Every operation
  * rounds its exact result to the nearest p-bit value, ties to the even
@@ -82,7 +85,7 @@ enum mp_leaf {        /* kernel for the products below the cutoff */
 enum mp_status {
     MP_OK = 0,
     MP_E_ARG = -1,    /* bad size, stride, pointer or enum */
-    MP_E_PREC = -2,   /* prec not 128, 256, 512 or 1024 */
+    MP_E_PREC = -2,   /* prec not 128 .. 8192 as above (or above 1024 where an entry says so) */
     MP_E_ALIAS = -3,  /* output buffer overlaps an input buffer */
     MP_E_NOMEM = -4,  /* device allocation failed */
     MP_E_DEVICE = -5, /* HIP error (launch failure or earlier asynchronous fault) */
@@ -183,6 +186,7 @@ int mp_plan_info(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff
  * bits at or above 2^(e_i - W_A) (2^(f_j - W_B)): its truncation error is below
  * that power of two.  window_out (host, 2 int32, may be NULL) gets
  * W_A, W_B.  Synchronises the stream (the window depends on the data).
+ * prec 128 .. 1024 only (MP_E_PREC above).
  */
 int mp_gemm_slice(int64_t m, int64_t l, int64_t n, int prec, int extra,
                   const uint32_t *A, int64_t lda, int64_t psa,
@@ -273,7 +277,7 @@ int mp_profile_read(int max, int *kind, int *op, int *L, double *units, int64_t 
  * Fill the rows x cols matrix X with seeded p-bit values uniform on (-1, 1):
  * x = +-W 2^-p, W a p-bit integer hashed from (seed, element index, limb),
  * normalised (so device-resident test and request operands need no host
- * copy).  Asynchronous.
+ * copy).  Asynchronous.  prec 128 .. 1024 only (MP_E_PREC above).
  */
 int mp_fill_uniform(int64_t rows, int64_t cols, int prec, uint32_t *X, int64_t ld, int64_t ps, uint64_t seed);
 

@@ -615,6 +615,7 @@ int mp_fill_uniform(int64_t rows, int64_t cols, int prec, uint32_t* X, int64_t l
 {
     int L, rc;
     if ((rc = check_prec(prec, &L))) return rc;
+    if (L > 32) return set_err(MP_E_PREC, "mp_fill_uniform takes prec 128 .. 1024");
     if ((rc = check_mat("X", X, rows, cols, ld, ps))) return rc;
     if (rows == 0 || cols == 0) return MP_OK;
     if ((rc = device_check())) return rc;

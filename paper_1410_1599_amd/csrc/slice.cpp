@@ -222,6 +222,7 @@ extern "C" int mp_gemm_slice(int64_t m, int64_t l, int64_t n, int prec, int extr
 {
     int L, rc;
     if ((rc = check_prec(prec, &L))) return rc;
+    if (L > 32) return set_err(MP_E_PREC, "the slice path takes prec 128 .. 1024");
     if (extra < 0 || extra > SLICE_MAX_EXTRA) return set_err(MP_E_ARG, "extra must be in 0..64");
     if (m < 0 || l < 0 || n < 0) return set_err(MP_E_ARG, "negative dimension");
     if ((rc = check_mat("A", A, m, l, lda, psa)) || (rc = check_mat("B", B, l, n, ldb, psb)) ||

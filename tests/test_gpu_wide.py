@@ -152,3 +152,18 @@ def test_wide_lotkin_8192_unpivoted():
     for i in range(n):
         v = mpnum.to_fraction(I.entry(xg, i, 0, p), p)
         assert abs(v - i) < tol, i
+
+
+def test_wide_precisions_refused_where_unsupported():
+    """The INT8-slice product and the device fill exist up to 1024 bits only:
+    they refuse wider precisions with MP_E_PREC and launch nothing."""
+    p = 2048
+    A = mp.to_device(I.uniform_pm1(3, 3, p, 1))
+    C = mp.empty(3, 3, p)
+    with pytest.raises(mp.MPError) as e:
+        mp.mp_gemm_slice(3, 3, 3, p, 64, A, A, C)
+    assert e.value.code == -2
+    with pytest.raises(mp.MPError) as e:
+        mp.mp_fill_uniform(3, 3, p, C, 1)
+    assert e.value.code == -2
+    assert not mp.to_host(C).any()
