@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--slice-steps", type=int, default=3, help="timed steps of the INT8-slice path (0: skip)")
+    ap.add_argument("--slice-one-pass", type=int, default=1,
+                    help="also time the slice product computing every diagonal in one pass (0: skip)")
     ap.add_argument("--lu", type=int, default=1, help="run the LU workload (n=512, 512 bits, panel 64, Winograd "
                                                      "cutoff 32, random and Hilbert inputs); 0: skip")
     ap.add_argument("--lu-paper", type=int, default=1,
@@ -224,17 +226,19 @@ def main():
         mm_ms = sum(r["ms"] for r in mm) / max(1, len(mm))
         mm_tops = mm[0]["units"] / (mm_ms * 1e-3) / 1e12 if mm else 0.0
         u0, ndiag, recomputed, ntiles, _ = mp.mp_slice_last()
-        # the same product computing every diagonal in one pass, for comparison
-        mp.mp_set_slice_guard(-1)
-        mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.slice_steps):
+        ts_one = None
+        if args.slice_one_pass:
+            # the same product computing every diagonal in one pass, for comparison
+            mp.mp_set_slice_guard(-1)
             mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
-        torch.cuda.synchronize()
-        ts_one = (time.perf_counter() - t1) / args.slice_steps
-        mp.mp_set_slice_guard(32)
-        mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.slice_steps):
+                mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
+            torch.cuda.synchronize()
+            ts_one = (time.perf_counter() - t1) / args.slice_steps
+            mp.mp_set_slice_guard(32)
+            mp.mp_gemm_slice(n, n, n, p, 64, dA, dB, dS)
         slice_res = {
             "value": 2.0 * n ** 3 / ts, "unit": "2mln/s", "ms_per_step": round(ts * 1e3, 3),
             "speedup_vs_limb": round(ms / (ts * 1e3), 3), "windows": list(win),
@@ -246,7 +250,7 @@ def main():
             "other_ms": round(sum(r["ms"] for r in srecs if r["kind"] == 3) / args.slice_steps, 3),
             "early_stop": {"u0": u0, "diagonals": ndiag, "tiles_recomputed": recomputed, "tiles": ntiles,
                            "second_pass_ms": round(sum(r["ms"] for r in mm2) / args.slice_steps, 3),
-                           "one_pass_ms_per_step": round(ts_one * 1e3, 3)},
+                           "one_pass_ms_per_step": round(ts_one * 1e3, 3) if ts_one else None},
         }
         slice_host = mp.to_host(dS)
         del dS
