@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--slice-steps", type=int, default=3, help="timed steps of the INT8-slice path (0: skip)")
     ap.add_argument("--slice-one-pass", type=int, default=1,
                     help="also time the slice product computing every diagonal in one pass (0: skip)")
+    ap.add_argument("--c2", type=int, default=1,
+                    help="time every algorithm on m=l=n=1023/1024 at 256 bits, uniform entries (0: skip)")
     ap.add_argument("--lu", type=int, default=1, help="run the LU workload (n=512, 512 bits, panel 64, Winograd "
                                                      "cutoff 32, random and Hilbert inputs); 0: skip")
     ap.add_argument("--lu-paper", type=int, default=1,
@@ -309,6 +311,27 @@ def main():
         lu_res["config"] = ("n=512 prec=512 panel=64 winograd cutoff=32, b = A*ones; factors and pivots are checked "
                             "bit for bit against the CPU oracle by the GPU tests")
 
+    # m = l = n = 1023 and 1024 at 256 bits, uniform entries (seeds 3/4): every
+    # algorithm at cutoff 64 with odd sizes peeled; parity with the CPU oracle is
+    # a GPU test
+    c2 = None
+    if args.c2:
+        c2 = {"config": "m=l=n in {1023, 1024}, 256 bits, uniform [-1,1) seeds 3/4, cutoff 64, peel; second of two runs"}
+        for nn in (1023, 1024):
+            dA2 = mp.to_device(I.uniform_pm1(nn, nn, 256, 3))
+            dB2 = mp.to_device(I.uniform_pm1(nn, nn, 256, 4))
+            dC2 = mp.empty(nn, nn, 256)
+            c2[nn] = {}
+            for name in ("simple", "block", "strassen", "winograd"):
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    mp.mp_gemm_ex(nn, nn, nn, 256, mp.ALGOS[name], 64, mp.PEEL, mp.LEAF_SIMPLE, dA2, dB2, dC2)
+                    torch.cuda.synchronize()
+                    tk = time.perf_counter() - t0
+                c2[nn][name] = {"ms": round(tk * 1e3, 3), "2mln_per_s": 2.0 * nn ** 3 / tk}
+            del dA2, dB2, dC2
+
     lu_paper = None
     if args.lu_paper:
         lu_paper = {"config": "n=1024, no pivoting, Winograd trailing updates with cutoff 32; b = A x with "
@@ -472,7 +495,7 @@ def main():
                                "seeds 6/7" % (n, p, args.algo, args.cutoff),
                    "m": n, "l": n, "n": n, "prec": p, "algo": args.algo, "cutoff": args.cutoff},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "algorithms": others, "slice": slice_res,
-        "accuracy": accuracy, "serve": serve_res, "lu": lu_res, "lu_paper": lu_paper, "lotkin_8192": lotkin_8192, "paper_grid": paper_grid,
+        "accuracy": accuracy, "serve": serve_res, "lu": lu_res, "c2_n1023_n1024": c2, "lu_paper": lu_paper, "lotkin_8192": lotkin_8192, "paper_grid": paper_grid,
     }
     print(json.dumps(out))
 
