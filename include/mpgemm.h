@@ -14,8 +14,9 @@
  * algorithms (here with partial pivoting).
  *
  * ------------------------------------------------------------------ numbers
- * prec p is 128, 256, 512, 1024, 2048, 4096 or 8192 bits (Section 3 uses
- * 128 to 8192); L = p / 32.  Up to 1024 bits a GPU lane holds one value; from
+ * prec p is 128, 256, 512, 1024, 2048, 4096, 8192 or 10240 bits (Section 3
+ * uses 128 to 8192, Section 4 also 8650; 10240 is the next width here above
+ * it); L = p / 32.  Up to 1024 bits a GPU lane holds one value; from
  * 2048 bits a whole wavefront does (its 64 lanes each hold L / 64 limbs), with
  * the same results.  A value is
  *     (-1)^s * M * 2^(e - p),   2^(p-1) <= M < 2^p   (M normalised),

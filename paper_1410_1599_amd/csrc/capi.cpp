@@ -105,8 +105,9 @@ int set_err(int code, const char* msg)
 
 int check_prec(int prec, int* L)
 {
-    if (prec != 128 && prec != 256 && prec != 512 && prec != 1024 && prec != 2048 && prec != 4096 && prec != 8192)
-        return set_err(MP_E_PREC, "prec must be 128, 256, 512, 1024, 2048, 4096 or 8192");
+    if (prec != 128 && prec != 256 && prec != 512 && prec != 1024 && prec != 2048 && prec != 4096 && prec != 8192 &&
+        prec != 10240)
+        return set_err(MP_E_PREC, "prec must be 128, 256, 512, 1024, 2048, 4096, 8192 or 10240");
     *L = prec / 32;
     return MP_OK;
 }

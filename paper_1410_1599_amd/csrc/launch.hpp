@@ -43,8 +43,9 @@ hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv,
 hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n,
                            hipStream_t s);
 
-// the same operations for p = 2048, 4096, 8192 bits (L = 64, 128, 256), one
-// value per wavefront (wide_kernels.hip); the launchers above forward to them
+// the same operations for p = 2048, 4096, 8192, 10240 bits (L = 64, 128, 256,
+// 320), one value per wavefront (wide_kernels.hip); the launchers above
+// forward to them
 hipError_t launch_gemm_wide(int L, const GemmTask* tasks, const int32_t* tile_task, int64_t ntiles, const Bases& bs,
                             int64_t grid, hipStream_t s);
 hipError_t launch_node_wide(int L, int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,

@@ -1,5 +1,5 @@
 // wide.hpp -- p-bit binary floating point held by a whole wavefront, for
-// p = 2048, 4096, 8192 (the paper's high precisions, Sections 3 and 4): the
+// p = 2048, 4096, 8192, 10240 (the paper's high precisions, Sections 3 and 4): the
 // same number format and rounding as mp_arith.hpp, one correctly rounded
 // result (to nearest, ties to even) per operation.
 //

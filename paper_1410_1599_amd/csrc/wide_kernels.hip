@@ -1,5 +1,5 @@
-// wide_kernels.hip -- the kernels of the product and of LU for p = 2048, 4096
-// and 8192 bits, one value per wavefront (wide.hpp).  They run the same
+// wide_kernels.hip -- the kernels of the product and of LU for p = 2048, 4096,
+// 8192 and 10240 bits, one value per wavefront (wide.hpp).  They run the same
 // scalar operations in the same order as the one-value-per-lane kernels
 // (gemm_kernels.hip, lu_kernels.hip), so the results are the same correctly
 // rounded sequence the CPU oracle forms; a workgroup of four waves walks the
@@ -244,6 +244,7 @@ k_lu_solve_w(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
     case 64: { constexpr int LL = 64; CALL; break; }   \
     case 128: { constexpr int LL = 128; CALL; break; } \
     case 256: { constexpr int LL = 256; CALL; break; } \
+    case 320: { constexpr int LL = 320; CALL; break; } \
     default: return hipErrorInvalidValue;              \
     }
 
@@ -289,6 +290,7 @@ hipError_t launch_node_wide(int L, int op, const NodeTask* tasks, const int32_t*
     case 64: return node_wide_L<64>(op, tasks, tile_task, ntiles, bs, g, s);
     case 128: return node_wide_L<128>(op, tasks, tile_task, ntiles, bs, g, s);
     case 256: return node_wide_L<256>(op, tasks, tile_task, ntiles, bs, g, s);
+    case 320: return node_wide_L<320>(op, tasks, tile_task, ntiles, bs, g, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,4 +1,4 @@
-"""GPU parity at 2048, 4096 and 8192 bits (one value per wavefront), bit for
+"""GPU parity at 2048, 4096, 8192 and 10240 bits (one value per wavefront), bit for
 bit against the Python oracle:
 
 * scalar mul/add/sub/div on adversarial operands (gaps around 0, 32, 64, p,
@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 from paper_1410_1599_amd import mp  # noqa: E402
 
-WIDE = [2048, 4096, 8192]
+WIDE = [2048, 4096, 8192, 10240]
 
 
 def sync():
@@ -115,7 +115,7 @@ def _gpu_solve(F, piv, b, p):
     return mp.to_host(db)
 
 
-@pytest.mark.parametrize("p", [2048, 8192])
+@pytest.mark.parametrize("p", [2048, 8192, 10240])
 @pytest.mark.parametrize("pivot", [True, False])
 def test_wide_lu_and_solve(p, pivot):
     n, panel, cut = 13, 5, 2
