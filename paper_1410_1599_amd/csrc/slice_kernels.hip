@@ -122,27 +122,14 @@ __device__ __forceinline__ uint32_t shifted_word(const uint32_t* m, int32_t sh, 
     return r ? funnel(hi, lo, r) : lo;
 }
 
-// one thread: 4 consecutive inner indices (k) of one outer index (row of A /
-// column of B); writes digit plane s at D[s * dps + outer * kpad + k]
+// balanced base-256 digits of 4 consecutive inner indices k = 4g .. 4g+3 of
+// one outer index o (row of A / column of B), 4 digits per word; zeros
+// outside the matrix (the padding of the digit planes)
 template <int L, int NW>
-__global__ void __launch_bounds__(256)
-k_slice_digits(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer, int64_t inner, int by_cols,
-               const int32_t* __restrict__ emax, int32_t W, int32_t S, int8_t* __restrict__ D, int64_t dps,
-               int64_t outer_pad, int64_t kpad)
+__device__ __forceinline__ void slice_digits_of(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer,
+                                                int64_t inner, int by_cols, const int32_t* __restrict__ emax,
+                                                int32_t W, int64_t o, int64_t g, uint32_t (&dig)[4][NW])
 {
-    const int64_t gidx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t ngroups = kpad >> 2;
-    // B (by_cols): consecutive threads take consecutive outer indices so the reads coalesce
-    int64_t o, g;
-    if (by_cols) {
-        o = gidx % outer_pad;
-        g = gidx / outer_pad;
-    } else {
-        g = gidx % ngroups;
-        o = gidx / ngroups;
-    }
-    if (o >= outer_pad || g >= ngroups) return;
-    uint32_t dig[4][NW];                             // balanced digits, 4 per word
 #pragma unroll
     for (int e = 0; e < 4; e++) {
         const int64_t k = 4 * g + e;
@@ -183,18 +170,66 @@ k_slice_digits(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t o
             dig[e][w] = out;
         }
     }
-    // digit plane s, 4 consecutive k in one dword
+}
+
+// digit s of the 4 indices as one dword (4 consecutive k)
+template <int NW>
+__device__ __forceinline__ uint32_t plane_word(const uint32_t (&dig)[4][NW], int s)
+{
+    const int w = s >> 2, b = s & 3;
+    uint32_t v = 0;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int q = 0; q < NW; q++) x = (q == w) ? dig[e][q] : x;
+        v |= ((x >> (8 * b)) & 0xffu) << (8 * e);
+    }
+    return v;
+}
+
+// rows of A: one thread per 4 consecutive k of one row (consecutive threads,
+// consecutive k: the reads and the digit-plane writes coalesce); writes digit
+// plane s at D[s * dps + o * kpad + k]
+template <int L, int NW>
+__global__ void __launch_bounds__(256)
+k_slice_digits(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
+               const int32_t* __restrict__ emax, int32_t W, int32_t S, int8_t* __restrict__ D, int64_t dps,
+               int64_t outer_pad, int64_t kpad)
+{
+    const int64_t gidx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t ngroups = kpad >> 2;
+    const int64_t g = gidx % ngroups, o = gidx / ngroups;
+    if (o >= outer_pad) return;
+    uint32_t dig[4][NW];
+    slice_digits_of<L, NW>(X, ld, ps, outer, inner, 0, emax, W, o, g, dig);
+    for (int s = 0; s < S; s++) *(uint32_t*)(D + (int64_t)s * dps + o * kpad + 4 * g) = plane_word<NW>(dig, s);
+}
+
+// columns of B: a workgroup takes 32 columns x 64 k.  Consecutive threads take
+// consecutive columns (the reads of B coalesce); each digit plane goes out
+// through an LDS tile so that every column's 64 digits are written as one
+// 64-byte row segment of the k-contiguous plane.
+constexpr int DC_COLS = 32, DC_GROUPS = 16, DC_THREADS = DC_COLS * DC_GROUPS;
+
+template <int L, int NW>
+__global__ void __launch_bounds__(DC_THREADS)
+k_slice_digits_cols(const uint32_t* __restrict__ X, int64_t ld, int64_t ps, int64_t outer, int64_t inner,
+                    const int32_t* __restrict__ emax, int32_t W, int32_t S, int8_t* __restrict__ D, int64_t dps,
+                    int64_t kpad)
+{
+    __shared__ uint32_t tile[DC_COLS][DC_GROUPS + 1];
+    const int tid = threadIdx.x;
+    const int ol = tid % DC_COLS, gl = tid / DC_COLS;
+    const int64_t o0 = (int64_t)blockIdx.x * DC_COLS, g0 = (int64_t)blockIdx.y * DC_GROUPS;
+    uint32_t dig[4][NW];
+    slice_digits_of<L, NW>(X, ld, ps, outer, inner, 1, emax, W, o0 + ol, g0 + gl, dig);
+    const int r = tid / DC_GROUPS, c = tid % DC_GROUPS;
     for (int s = 0; s < S; s++) {
-        const int w = s >> 2, b = s & 3;
-        uint32_t v = 0;
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            uint32_t x = 0;
-#pragma unroll
-            for (int q = 0; q < NW; q++) x = (q == w) ? dig[e][q] : x;
-            v |= ((x >> (8 * b)) & 0xffu) << (8 * e);
-        }
-        *(uint32_t*)(D + (int64_t)s * dps + o * kpad + 4 * g) = v;
+        tile[ol][gl] = plane_word<NW>(dig, s);
+        __syncthreads();
+        *(uint32_t*)(D + (int64_t)s * dps + (o0 + r) * kpad + 4 * (g0 + c)) = tile[r][c];
+        __syncthreads();
     }
 }
 
@@ -521,14 +556,27 @@ hipError_t launch_slice_digits(int L, const uint32_t* X, int64_t ld, int64_t ps,
                                int by_cols, const int32_t* emax, int32_t W, int32_t S, int8_t* D, int64_t dps,
                                int64_t outer_pad, int64_t kpad, hipStream_t s)
 {
+    // NW = words of the W-bit window plus the recoding headroom, per precision
+    if (by_cols) {
+        // outer_pad is a multiple of the 256-row tile, kpad of the 64-deep k step
+        if (outer_pad % DC_COLS || (kpad / 4) % DC_GROUPS) return hipErrorInvalidValue;
+        const dim3 g((unsigned)(outer_pad / DC_COLS), (unsigned)(kpad / 4 / DC_GROUPS)), b(DC_THREADS);
+        switch (L) {
+        case 4: hipLaunchKernelGGL((k_slice_digits_cols<4, SLICE_NW4>), g, b, 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, kpad); break;
+        case 8: hipLaunchKernelGGL((k_slice_digits_cols<8, SLICE_NW8>), g, b, 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, kpad); break;
+        case 16: hipLaunchKernelGGL((k_slice_digits_cols<16, SLICE_NW16>), g, b, 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, kpad); break;
+        case 32: hipLaunchKernelGGL((k_slice_digits_cols<32, SLICE_NW32>), g, b, 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, kpad); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int64_t threads = outer_pad * (kpad / 4);
     const dim3 g((unsigned)((threads + 255) / 256));
-    // NW = words of the W-bit window plus the recoding headroom, per precision
     switch (L) {
-    case 4: hipLaunchKernelGGL((k_slice_digits<4, SLICE_NW4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
-    case 8: hipLaunchKernelGGL((k_slice_digits<8, SLICE_NW8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
-    case 16: hipLaunchKernelGGL((k_slice_digits<16, SLICE_NW16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
-    case 32: hipLaunchKernelGGL((k_slice_digits<32, SLICE_NW32>), g, dim3(256), 0, s, X, ld, ps, outer, inner, by_cols, emax, W, S, D, dps, outer_pad, kpad); break;
+    case 4: hipLaunchKernelGGL((k_slice_digits<4, SLICE_NW4>), g, dim3(256), 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, outer_pad, kpad); break;
+    case 8: hipLaunchKernelGGL((k_slice_digits<8, SLICE_NW8>), g, dim3(256), 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, outer_pad, kpad); break;
+    case 16: hipLaunchKernelGGL((k_slice_digits<16, SLICE_NW16>), g, dim3(256), 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, outer_pad, kpad); break;
+    case 32: hipLaunchKernelGGL((k_slice_digits<32, SLICE_NW32>), g, dim3(256), 0, s, X, ld, ps, outer, inner, emax, W, S, D, dps, outer_pad, kpad); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
