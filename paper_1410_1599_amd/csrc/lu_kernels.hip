@@ -25,10 +25,13 @@ constexpr int PIV_THREADS = 256;
 
 // The pivot of column c is the first row index r >= c of the largest |a_rc|
 // (exact comparison; ties to the smaller index): each of the NT threads scans
-// a strided share of the rows keeping its best in registers, then the
-// candidates (value and index) are reduced in LDS.  piv[c] = r, info = c + 1
-// for the first exactly zero pivot; then the same workgroup swaps rows c and
-// r over the panel columns [j0, je).  Called by all NT threads of one
+// a strided share of the rows keeping its best in registers.  The candidates
+// are then reduced without a comparison tree: one LDS atomic max over a
+// 64-bit key (exponent, top limb) finds the largest key, the threads holding
+// it list themselves, and one thread settles that short list (usually one
+// entry) by full comparison, ties to the smaller index.  piv[c] = r, info =
+// c + 1 for the first exactly zero pivot; then the same workgroup swaps rows c
+// and r over the panel columns [j0, je).  Called by all NT threads of one
 // workgroup.
 template <int L, int NT>
 __device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int64_t c, int64_t j0, int64_t je,
@@ -36,6 +39,9 @@ __device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int6
 {
     __shared__ uint32_t sv[L + 2][NT];
     __shared__ int32_t sidx[NT];
+    __shared__ unsigned long long skey;
+    __shared__ int32_t scount, sbest;
+    __shared__ int32_t scand[NT];
     const int tid = threadIdx.x;
     int32_t best = -1;
     MP<L> bv = mp_zero<L>();
@@ -51,42 +57,42 @@ __device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int6
     sv[L][tid] = (uint32_t)bv.e;
     sv[L + 1][tid] = bv.s;
     sidx[tid] = best;
+    if (tid == 0) {
+        skey = 0;
+        scount = 0;
+    }
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            const int32_t i1 = sidx[tid], i2 = sidx[tid + s];
-            bool take = false;
-            if (i2 >= 0) {
-                if (i1 < 0) {
-                    take = true;
-                } else {
-                    MP<L> x1, x2;
+    // |x| grows with (exponent, top limb) among nonzero values (|e| < 2^29);
+    // zero has key 0
+    const unsigned long long key =
+        is_zero<L>(bv) ? 0ull : (((unsigned long long)(uint32_t)(bv.e + (1 << 30)) << 32) | bv.m[L - 1]);
+    if (best >= 0) atomicMax(&skey, key);
+    __syncthreads();
+    if (best >= 0 && key == skey) scand[atomicAdd(&scount, 1)] = tid;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t bi = -1;
+        MP<L> bx = mp_zero<L>();
+        for (int q = 0; q < scount; q++) {
+            const int u = scand[q];
+            MP<L> x;
 #pragma unroll
-                    for (int q = 0; q < L; q++) {
-                        x1.m[q] = sv[q][tid];
-                        x2.m[q] = sv[q][tid + s];
-                    }
-                    x1.e = (int32_t)sv[L][tid];
-                    x2.e = (int32_t)sv[L][tid + s];
-                    x1.s = sv[L + 1][tid];
-                    x2.s = sv[L + 1][tid + s];
-                    const int cm = cmp_abs<L>(x2, x1);
-                    take = cm > 0 || (cm == 0 && i2 < i1);
-                }
-            }
-            if (take) {
-#pragma unroll
-                for (int q = 0; q < L + 2; q++) sv[q][tid] = sv[q][tid + s];
-                sidx[tid] = i2;
+            for (int w = 0; w < L; w++) x.m[w] = sv[w][u];
+            x.e = (int32_t)sv[L][u];
+            x.s = sv[L + 1][u];
+            const int32_t iu = sidx[u];
+            const int cm = bi < 0 ? 1 : cmp_abs<L>(x, bx);
+            if (cm > 0 || (cm == 0 && iu < bi)) {
+                bi = iu;
+                bx = x;
             }
         }
-        __syncthreads();
+        sbest = bi;
+        piv[c] = bi;
+        if (is_zero<L>(bx) && info[0] == 0) info[0] = (int32_t)(c + 1);
     }
-    const int64_t r = sidx[0];
-    if (tid == 0) {
-        piv[c] = (int32_t)r;
-        if (sv[L - 1][0] == 0 && info[0] == 0) info[0] = (int32_t)(c + 1);
-    }
+    __syncthreads();
+    const int64_t r = sbest;
     if (r != c) {
         uint32_t* p = base_ptr(bs, a.base) + a.off;
         const int64_t w = je - j0;
