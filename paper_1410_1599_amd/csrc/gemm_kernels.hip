@@ -86,24 +86,28 @@ k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ ti
         if (i >= T.m || j >= T.n) continue;
         uint32_t* C = wave_uniform(base_ptr(bs, T.C.base)) + T.C.off + i * T.C.ld + j;
         MP<L> c = T.accum ? load<L>(C, T.C.ps, 0) : mp_zero<L>();
+        // a_ik at A + i * ia + k * ka: row-major, or a transposed copy (T.at)
+        const int64_t ia = T.at ? 1 : T.A.ld, ka = T.at ? T.A.ld : 1;
         if (T.A.ps < (1 << 30) && T.B.ps < (1 << 30)) {
             // every offset inside a plane fits 32 bits
             const uint32_t* A = ref_ptr<L>(bs, T.A);
             const uint32_t* B = ref_ptr<L>(bs, T.B);
-            const uint32_t oa = (uint32_t)i * (uint32_t)T.A.ld;
+            uint32_t oa = (uint32_t)i * (uint32_t)ia;
+            const uint32_t aks = (uint32_t)ka;
             const uint32_t bld = (uint32_t)T.B.ld;
             uint32_t ob = (uint32_t)j;
             for (int k = 0; k < T.l; k++) {
-                const MP<L> a = load_planes<L>(A, T.A.ps, oa + (uint32_t)k);
+                const MP<L> a = load_planes<L>(A, T.A.ps, oa);
                 const MP<L> b = load_planes<L>(B, T.B.ps, ob);
+                oa += aks;
                 ob += bld;
                 c = add_rn<L>(c, mul_rn<L>(a, b));
             }
         } else {
-            const uint32_t* A = ref_ptr<L>(bs, T.A) + i * T.A.ld;
+            const uint32_t* A = ref_ptr<L>(bs, T.A) + i * ia;
             const uint32_t* B = ref_ptr<L>(bs, T.B) + j;
             for (int k = 0; k < T.l; k++) {
-                const MP<L> a = load<L>(A, T.A.ps, k);
+                const MP<L> a = load<L>(A, T.A.ps, (int64_t)k * ka);
                 const MP<L> b = load<L>(B, T.B.ps, (int64_t)k * T.B.ld);
                 c = add_rn<L>(c, mul_rn<L>(a, b));
             }
@@ -245,6 +249,37 @@ k_fill_uniform(uint32_t* X, int64_t ld, int64_t ps, int64_t rows, int64_t cols, 
     store<L>(X, ps, i * ld + j, r);
 }
 
+// ------------------------------------------------------------------ transpose
+
+// out0 (cols x rows) := in0 (rows x cols) transposed, every one of the nplanes
+// planes (limbs, exponent, sign) copied word for word.  A tile is a 16 x 16
+// block of the source; it passes through LDS so that both the reads (along
+// the source rows) and the writes (along the destination rows) are runs of
+// 16 consecutive words.
+__global__ void __launch_bounds__(256)
+k_transpose(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs,
+            int nplanes)
+{
+    __shared__ uint32_t tile[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const NodeTask& T = tasks[tile_task[t]];
+        const int64_t lt = t - T.tile0;
+        const int64_t nbj = (T.cols + 15) / 16;
+        const int64_t i0 = (lt / nbj) * 16, j0 = (lt % nbj) * 16;
+        const uint32_t* src = base_ptr(bs, T.in[0].base) + T.in[0].off;
+        uint32_t* dst = base_ptr(bs, T.out[0].base) + T.out[0].off;
+        for (int q = 0; q < nplanes; q++) {
+            const int64_t si = i0 + ty, sj = j0 + tx;
+            if (si < T.rows && sj < T.cols) tile[ty][tx] = src[q * T.in[0].ps + si * T.in[0].ld + sj];
+            __syncthreads();
+            const int64_t di = j0 + ty, dj = i0 + tx;           // destination row = source column
+            if (di < T.cols && dj < T.rows) dst[q * T.out[0].ps + di * T.out[0].ld + dj] = tile[tx][ty];
+            __syncthreads();
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t* X, int64_t count, int32_t value)
@@ -334,6 +369,11 @@ static hipError_t node_launch_L(int op, const NodeTask* tasks, const int32_t* ti
 hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles,
                        const Bases& bs, int64_t grid, hipStream_t s)
 {
+    if (op == OP_TRANSPOSE) {           // word copies: one kernel for every precision
+        if (ntiles <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_transpose, dim3((unsigned)grid), dim3(256), 0, s, tasks, tile_task, ntiles, bs, L + 2);
+        return hipGetLastError();
+    }
     if (L >= 64) return launch_node_wide(L, op, tasks, tile_task, ntiles, bs, grid, s);
     switch (L) {
     case 4: return node_launch_L<4>(op, tasks, tile_task, ntiles, bs, grid, s);

@@ -54,7 +54,7 @@ struct Builder {
     const PlanKey& k;
     int L;
     int64_t ws = 0;
-    std::vector<std::vector<NodeTask>> pads, opsA, opsB, combs, crops;
+    std::vector<std::vector<NodeTask>> pads, opsA, opsB, trans, combs, crops;
     std::vector<std::vector<GemmTask>> fixes;
     std::vector<GemmTask> leaves;
     double n_mul = 0, n_addsub = 0;
@@ -73,7 +73,7 @@ struct Builder {
     {
         const size_t need = (size_t)d + 1;
         if (pads.size() < need) {
-            pads.resize(need); opsA.resize(need); opsB.resize(need);
+            pads.resize(need); opsA.resize(need); opsB.resize(need); trans.resize(need);
             combs.resize(need); crops.resize(need); fixes.resize(need);
         }
         depth = std::max(depth, d + 1);
@@ -88,12 +88,12 @@ struct Builder {
     }
 
     void gemm_task(std::vector<GemmTask>& v, const MatRef& A, const MatRef& B, const MatRef& C,
-                   int64_t m, int64_t l, int64_t n, int accum)
+                   int64_t m, int64_t l, int64_t n, int accum, int at = 0)
     {
         if (m <= 0 || n <= 0) return;
         GemmTask t{};
         t.A = A; t.B = B; t.C = C;
-        t.m = (int32_t)m; t.l = (int32_t)l; t.n = (int32_t)n; t.accum = accum;
+        t.m = (int32_t)m; t.l = (int32_t)l; t.n = (int32_t)n; t.accum = accum; t.at = at;
         t.tcl = (k.leaf == 1) ? 6 : std::min(6, ceil_log2(n));
         v.push_back(t);
         n_mul += (double)m * l * n;
@@ -192,16 +192,33 @@ struct Builder {
             tc.out[0] = C11; tc.out[1] = C12; tc.out[2] = C21; tc.out[3] = C22;
             combs[d].push_back(tc);
         }
-        // peeled borders: Simple over the full inner size, written into C directly
-        if (an == PEEL) gemm_task(leaves, A, sub(B, 0, n - 1), sub(C, 0, n - 1), mi, l, 1, 0);
+        // peeled borders: Simple over the full inner size, written into C directly.
+        // The column border gives each lane a row of A to walk along k; with the
+        // Simple leaf it reads a transposed copy of A[0:mi, 0:l] instead, so
+        // that a wave's loads of one k are consecutive words (the same values,
+        // the same order: the results do not change)
+        if (an == PEEL) {
+            if (k.leaf == 0 && mi > 1) {
+                const MatRef At = alloc(l, mi);
+                NodeTask tt = node(mi, l);
+                tt.in[0] = A;
+                tt.out[0] = At;
+                trans[d].push_back(tt);
+                gemm_task(leaves, At, sub(B, 0, n - 1), sub(C, 0, n - 1), mi, l, 1, 0, 1);
+            } else {
+                gemm_task(leaves, A, sub(B, 0, n - 1), sub(C, 0, n - 1), mi, l, 1, 0);
+            }
+        }
         if (am == PEEL) gemm_task(leaves, sub(A, m - 1, 0), B, sub(C, m - 1, 0), 1, l, n, 0);
         // peeled inner index: C[0:mi, 0:ni] += a_{i,l-1} b_{l-1,j}, after the combination
         if (al == PEEL) gemm_task(fixes[d], sub(A, 0, l - 1), sub(B, l - 1, 0), C, mi, 1, ni, 1);
     }
 };
 
-int64_t node_tiles(const NodeTask& t)
+int64_t node_tiles(const NodeTask& t, int op)
 {
+    if (op == OP_TRANSPOSE)      // 16 x 16 blocks of the source
+        return ((int64_t)(t.rows + 15) / 16) * ((t.cols + 15) / 16);
     return ((int64_t)t.rows * t.cols + NODE_TILE - 1) / NODE_TILE;
 }
 
@@ -226,7 +243,7 @@ void assemble(Plan& P, Builder& b)
         for (auto& t : v) {
             t.tile0 = tile;
             s.units += (double)t.rows * t.cols;
-            const int64_t nt = node_tiles(t);
+            const int64_t nt = node_tiles(t, op);
             const int32_t idx = (int32_t)P.node.size();
             P.node.push_back(t);
             for (int64_t q = 0; q < nt; q++) P.tiles.push_back(idx);
@@ -256,13 +273,26 @@ void assemble(Plan& P, Builder& b)
         add_node_step(b.pads[d], OP_PADCOPY);
         add_node_step(b.opsA[d], wino ? OP_WINO_A : OP_STR_A);
         add_node_step(b.opsB[d], wino ? OP_WINO_B : OP_STR_B);
+        add_node_step(b.trans[d], OP_TRANSPOSE);
     }
     // the leaf launch's tasks are independent; a lane's work is its task's
     // inner length, so the long ones (peeled borders, Simple over the full
     // inner size) go first and overlap with the many short leaves instead of
-    // trailing them
+    // trailing them.  The leaf kernels give each of the 8 XCDs one contiguous
+    // eighth of the tile list, so the tasks, longest first, are dealt round
+    // robin into 8 runs laid end to end: every XCD starts on its share of the
+    // long tasks (all of them at the head of one list would leave them to one
+    // XCD), and a task's tiles stay together.
     std::stable_sort(b.leaves.begin(), b.leaves.end(),
                      [](const GemmTask& x, const GemmTask& y) { return x.l > y.l; });
+    {
+        constexpr size_t NX = 8;
+        std::vector<GemmTask> dealt;
+        dealt.reserve(b.leaves.size());
+        for (size_t x = 0; x < NX; x++)
+            for (size_t i = x; i < b.leaves.size(); i += NX) dealt.push_back(b.leaves[i]);
+        b.leaves.swap(dealt);
+    }
     add_gemm_step(b.leaves, k.leaf == 1 ? 1 : 0);
     for (int d = b.depth - 1; d >= 0; d--) {
         add_node_step(b.combs[d], wino ? OP_WINO_C : OP_STR_C);
@@ -333,7 +363,8 @@ bool validate_plan(const Plan& P, const char** why)
     const int64_t* size = P.base_words.data();
     const int32_t nb = (int32_t)P.base_words.size();
     for (const GemmTask& t : P.gemm) {
-        if (!view_ok(t.A, t.m, t.l, L, size, nb) || !view_ok(t.B, t.l, t.n, L, size, nb) || !view_ok(t.C, t.m, t.n, L, size, nb)) {
+        const bool aok = t.at ? view_ok(t.A, t.l, t.m, L, size, nb) : view_ok(t.A, t.m, t.l, L, size, nb);
+        if (!aok || !view_ok(t.B, t.l, t.n, L, size, nb) || !view_ok(t.C, t.m, t.n, L, size, nb)) {
             *why = "gemm task out of bounds";
             return false;
         }
@@ -343,10 +374,11 @@ bool validate_plan(const Plan& P, const char** why)
             if (s.kind == 0) continue;
             const NodeTask& t = P.node[(size_t)q];
             int nin = 0, nout = 0;
-            int64_t irows = t.rows, icols = t.cols;
+            int64_t irows = t.rows, icols = t.cols, orows = t.rows, ocols = t.cols;
             switch (s.op) {
             case OP_ADD: case OP_SUB: case OP_MUL: case OP_DIV: nin = 2; nout = 1; break;
             case OP_COPY: nin = 1; nout = 1; break;
+            case OP_TRANSPOSE: nin = 1; nout = 1; orows = t.cols; ocols = t.rows; break;
             case OP_PADCOPY: nin = 1; nout = 1; irows = t.aux0; icols = t.aux1; break;
             case OP_WINO_A: case OP_WINO_B: nin = 4; nout = 4; break;
             case OP_STR_A: case OP_STR_B: nin = 4; nout = 5; break;
@@ -356,7 +388,7 @@ bool validate_plan(const Plan& P, const char** why)
             for (int i = 0; i < nin; i++)
                 if (!view_ok(t.in[i], irows, icols, L, size, nb)) { *why = "node input out of bounds"; return false; }
             for (int i = 0; i < nout; i++)
-                if (!view_ok(t.out[i], t.rows, t.cols, L, size, nb)) { *why = "node output out of bounds"; return false; }
+                if (!view_ok(t.out[i], orows, ocols, L, size, nb)) { *why = "node output out of bounds"; return false; }
         }
     }
     for (const Step& s : P.steps) {

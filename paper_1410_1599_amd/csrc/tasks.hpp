@@ -41,7 +41,8 @@ struct GemmTask {
     MatRef A, B, C;
     int32_t m, l, n, accum;
     int32_t tcl;              // tile width 2^tcl columns (the Block kernel needs 6)
-    int32_t pad_;
+    int32_t at;               // A stored transposed: element (i, k) of A is element (k, i) of the view
+                              // (Simple kernels only)
     int64_t tile0;            // first tile of this task in the launch
 };
 
@@ -59,7 +60,8 @@ enum NodeOp : int32_t {
     OP_STR_A = 9,             // the five A-side sums of Strassen
     OP_STR_B = 10,            // the five B-side sums of Strassen
     OP_STR_C = 11,            // C11..C22 from P1..P7
-    NUM_NODE_OPS = 12
+    OP_TRANSPOSE = 12,        // out0 (cols x rows) = in0 (rows x cols) transposed, every plane copied
+    NUM_NODE_OPS = 13
 };
 
 struct NodeTask {

@@ -60,7 +60,10 @@ k_gemm_w(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_ta
             const int64_t j = (lt % tn) * tc + (el & (tc - 1));
             if (i >= T.m || j >= T.n) continue;
             WMP<L> c = T.accum ? wld<L>(bs, T.C, i, j) : wzero<L>();
-            for (int k = 0; k < T.l; k++) c = add_rn<L>(c, mul_rn<L>(wld<L>(bs, T.A, i, k), wld<L>(bs, T.B, k, j)));
+            for (int k = 0; k < T.l; k++) {
+                const WMP<L> a = T.at ? wld<L>(bs, T.A, k, i) : wld<L>(bs, T.A, i, k);   // a transposed copy, or not
+                c = add_rn<L>(c, mul_rn<L>(a, wld<L>(bs, T.B, k, j)));
+            }
             wst<L>(bs, T.C, i, j, c);
         }
     }
