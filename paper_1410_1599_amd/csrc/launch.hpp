@@ -34,7 +34,16 @@ hipError_t launch_fill_i32(int32_t* X, int64_t count, int32_t value, hipStream_t
 // search == 0: no row exchange, the pivot is a_cc
 hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
                                 int32_t* piv, int32_t* info, int search, hipStream_t s);
-hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, hipStream_t s);
+// next: 0 plain; 1 also store each row's key of its new a_i,c+1 in keys[i - c
+// - 1] (n 64-bit words) for launch_lu_pivot_keys of column c + 1 < je; 2 also
+// check a_c+1,c+1 for the unpivoted LU.  Precisions of 2048 bits and more
+// take next = 0 only.
+hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, int32_t* piv,
+                               int32_t* info, unsigned long long* keys, int next, hipStream_t s);
+// pivot search of column c from the keys left by the elimination of column
+// c - 1, then the swap inside the panel [j0, je); below 2048 bits only
+hipError_t launch_lu_pivot_keys(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                                int32_t* piv, int32_t* info, const unsigned long long* keys, hipStream_t s);
 hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t kb, int64_t je, int64_t n,
                          hipStream_t s);
 // piv[k0 .. k1) applied in order to the columns [c0, c1) and [c2, c3)

@@ -38,11 +38,18 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
     int rc = MP_OK;
     const int64_t m2max = n > panel ? n - panel : 0;
     const size_t pwords = (size_t)(L + 2) * (size_t)(m2max * m2max);
-    // aux buffer: the trailing product P, then one int32 status word
-    uint32_t* aux = workspace(pwords + 64, s, WS_LU, &rc);
+    // aux buffer: the trailing product P, one int32 status word and the n
+    // 64-bit pivot keys of the column steps ((L + 2) is even, so the keys are
+    // 8-byte aligned)
+    uint32_t* aux = workspace(pwords + 64 + 2 * (size_t)n, s, WS_LU, &rc);
     if (rc) return rc;
     int32_t* status = info_dev ? info_dev : (int32_t*)(aux + pwords);
+    unsigned long long* keys = (unsigned long long*)(aux + pwords + 64);
     MPG_TRY(launch_fill_i32(status, 1, 0, s));
+    // below 2048 bits the elimination of column c leaves the keys of column
+    // c + 1 (or, unpivoted, checks its diagonal), so a pivot step inside a
+    // panel reads the keys instead of the column
+    const bool keyed = L < 64;
     Bases bs{};
     bs.p[BASE_A] = A;
     const MatRef a{BASE_A, 0, 0, lda, psa};
@@ -53,8 +60,12 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
             // pivot search and the swap inside the panel; then multipliers and
             // the panel's rank-one update (a zero pivot leaves a zero column, whose
             // quotients and updates are exact no-ops)
-            MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, pivot, s));
-            MPG_TRY(launch_lu_eliminate(L, bs, a, n, c, je, s));
+            if (c == j0 || !keyed)
+                MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, pivot, s));
+            else if (pivot)
+                MPG_TRY(launch_lu_pivot_keys(L, bs, a, n, c, j0, je, piv, status, keys, s));
+            const int next = (keyed && c + 1 < je) ? (pivot ? 1 : 2) : 0;
+            MPG_TRY(launch_lu_eliminate(L, bs, a, n, c, je, piv, status, keys, next, s));
         }
         if (pivot) MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, je, n, s));
         if (je >= n) break;

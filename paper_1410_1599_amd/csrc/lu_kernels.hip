@@ -24,18 +24,16 @@ __device__ __forceinline__ void stm(const Bases& bs, const MatRef& r, int64_t i,
 constexpr int PIV_THREADS = 256;
 
 // The pivot of column c is the first row index r >= c of the largest |a_rc|
-// (exact comparison; ties to the smaller index): each of the NT threads scans
-// a strided share of the rows keeping its best in registers.  The candidates
-// are then reduced without a comparison tree: one LDS atomic max over a
-// 64-bit key (exponent, top limb) finds the largest key, the threads holding
-// it list themselves, and one thread settles that short list (usually one
-// entry) by full comparison, ties to the smaller index.  piv[c] = r, info =
-// c + 1 for the first exactly zero pivot; then the same workgroup swaps rows c
-// and r over the panel columns [j0, je).  Called by all NT threads of one
-// workgroup.
+// (exact comparison; ties to the smaller index).  Each of the NT threads of a
+// workgroup brings its best (index, value) over a share of the rows, visited
+// in ascending order (best = -1: no rows).  The candidates are reduced without
+// a comparison tree: one LDS atomic max over a 64-bit key (exponent, top limb)
+// finds the largest key, the threads holding it list themselves, and one
+// thread settles that short list (usually one entry) by full comparison, ties
+// to the smaller index.  Writes piv[c] = r and info = c + 1 for the first
+// exactly zero pivot; returns r in every thread.
 template <int L, int NT>
-__device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int64_t c, int64_t j0, int64_t je,
-                               int32_t* piv, int32_t* info)
+__device__ int64_t settle_pivot(int32_t best, const MP<L>& bv, int64_t c, int32_t* piv, int32_t* info)
 {
     __shared__ uint32_t sv[L + 2][NT];
     __shared__ int32_t sidx[NT];
@@ -43,15 +41,6 @@ __device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int6
     __shared__ int32_t scount, sbest;
     __shared__ int32_t scand[NT];
     const int tid = threadIdx.x;
-    int32_t best = -1;
-    MP<L> bv = mp_zero<L>();
-    for (int64_t i = c + tid; i < n; i += NT) {
-        const MP<L> v = ldm<L>(bs, a, i, c);
-        if (best < 0 || cmp_abs<L>(v, bv) > 0) {
-            best = (int32_t)i;
-            bv = v;
-        }
-    }
 #pragma unroll
     for (int q = 0; q < L; q++) sv[q][tid] = bv.m[q];
     sv[L][tid] = (uint32_t)bv.e;
@@ -92,19 +81,40 @@ __device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int6
         if (is_zero<L>(bx) && info[0] == 0) info[0] = (int32_t)(c + 1);
     }
     __syncthreads();
-    const int64_t r = sbest;
-    if (r != c) {
-        uint32_t* p = base_ptr(bs, a.base) + a.off;
-        const int64_t w = je - j0;
-        for (int64_t e = tid; e < w * (L + 2); e += NT) {
-            const int64_t j = j0 + e % w, q = e / w;
-            uint32_t* x = p + q * a.ps + c * a.ld + j;
-            uint32_t* y = p + q * a.ps + r * a.ld + j;
-            const uint32_t t = *x;
-            *x = *y;
-            *y = t;
+    return sbest;
+}
+
+// Exchange rows c and r (r != c) over the panel columns [j0, je), every
+// plane: a thread takes whole columns, loading both rows' words before it
+// stores any (the two rows never overlap).
+template <int L, int NT>
+__device__ void swap_rows(const Bases& bs, const MatRef& a, int64_t c, int64_t r, int64_t j0, int64_t je)
+{
+    for (int64_t j = j0 + threadIdx.x; j < je; j += NT) {
+        const MP<L> x = ldm<L>(bs, a, c, j), y = ldm<L>(bs, a, r, j);
+        stm<L>(bs, a, c, j, y);
+        stm<L>(bs, a, r, j, x);
+    }
+}
+
+// pivot search of column c over the rows [c, n) (each thread a strided
+// share), then the swap of rows c and r over the panel columns [j0, je)
+template <int L, int NT>
+__device__ void pivot_and_swap(const Bases& bs, const MatRef& a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                               int32_t* piv, int32_t* info)
+{
+    const int tid = threadIdx.x;
+    int32_t best = -1;
+    MP<L> bv = mp_zero<L>();
+    for (int64_t i = c + tid; i < n; i += NT) {
+        const MP<L> v = ldm<L>(bs, a, i, c);
+        if (best < 0 || cmp_abs<L>(v, bv) > 0) {
+            best = (int32_t)i;
+            bv = v;
         }
     }
+    const int64_t r = settle_pivot<L, NT>(best, bv, c, piv, info);
+    if (r != c) swap_rows<L, NT>(bs, a, c, r, j0, je);
 }
 
 // search == 0: the paper's LU without row exchanges: the pivot is a_cc
@@ -121,19 +131,91 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
     }
 }
 
-// one workgroup per row i in (c, n): l = a_ic / a_cc by one lane, shared in
+// The pivot of column c when the elimination of column c - 1 has left each
+// row's 64-bit key (exponent, top limb; 0 for zero) in keys[i - c] for the
+// rows i in [c, n): the keys are read coalesced, KR per thread at a time, the
+// largest is found in LDS, and only the rows holding it have their values
+// read and compared in full (ascending, first index on ties); then the pivot
+// is settled and rows c and r exchanged over the panel columns [j0, je) as by
+// the full search.
+template <int L>
+__global__ void __launch_bounds__(PIV_THREADS)
+k_lu_pivot_keys(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info,
+                const unsigned long long* keys)
+{
+    constexpr int NT = PIV_THREADS, KR = 4;
+    const int tid = threadIdx.x;
+    const int64_t m = n - c;
+    __shared__ unsigned long long smax;
+    if (tid == 0) smax = 0;
+    __syncthreads();
+    unsigned long long km = 0;
+    for (int64_t k0 = 0; k0 < m; k0 += KR * NT) {
+        unsigned long long kr[KR];
+#pragma unroll
+        for (int u = 0; u < KR; u++) {
+            const int64_t k = k0 + u * NT + tid;
+            kr[u] = k < m ? keys[k] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < KR; u++) km = kr[u] > km ? kr[u] : km;
+    }
+    atomicMax(&smax, km);
+    __syncthreads();
+    const unsigned long long kmax = smax;
+    int32_t best = -1;
+    MP<L> bv = mp_zero<L>();
+    for (int64_t k0 = 0; k0 < m; k0 += KR * NT) {
+        unsigned long long kr[KR];
+#pragma unroll
+        for (int u = 0; u < KR; u++) {
+            const int64_t k = k0 + u * NT + tid;
+            kr[u] = k < m ? keys[k] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < KR; u++) {
+            const int64_t k = k0 + u * NT + tid;
+            if (k < m && kr[u] == kmax) {
+                const MP<L> v = ldm<L>(bs, a, c + k, c);
+                if (best < 0 || cmp_abs<L>(v, bv) > 0) {
+                    best = (int32_t)(c + k);
+                    bv = v;
+                }
+            }
+        }
+    }
+    const int64_t r = settle_pivot<L, NT>(best, bv, c, piv, info);
+    if (r != c) swap_rows<L, NT>(bs, a, c, r, j0, je);
+}
+
+// One workgroup per row i in (c, n): l = a_ic / a_cc by one lane, shared in
 // LDS, then a_ij := a_ij - l a_cj for the panel columns j in (c, je); a zero
-// pivot skips the column (no quotient, no update)
+// pivot skips the column (no quotient, no update).
+//
+// next == ELIM_NEXT_KEYS (c + 1 < je): lane 0 of each workgroup, which has
+// just formed its row's new a_i,c+1, stores the row's 64-bit key (exponent,
+// top limb; 0 for zero) in keys[i - c - 1] for the pivot step of column c + 1.
+//
+// next == ELIM_NEXT_DIAG (no row exchanges): the owner of row c + 1 checks its
+// new a_c+1,c+1 for zero (info) and sets piv[c + 1] = c + 1.
 constexpr int ELIM_THREADS = 64;
+constexpr int ELIM_PLAIN = 0, ELIM_NEXT_KEYS = 1, ELIM_NEXT_DIAG = 2;
 
 template <int L>
 __global__ void __launch_bounds__(ELIM_THREADS)
-k_lu_eliminate(Bases bs, MatRef a, int64_t c, int64_t je)
+k_lu_eliminate(Bases bs, MatRef a, int64_t c, int64_t je, int32_t* piv, int32_t* info, unsigned long long* keys,
+               int next)
 {
     __shared__ uint32_t sl[L + 2];
     __shared__ int32_t skip;
+    const int tid = threadIdx.x;
     const int64_t i = c + 1 + blockIdx.x;
-    if (threadIdx.x == 0) {
+    // this lane's first pair of operands is loaded while lane 0 divides
+    const int64_t jf = c + 1 + tid;
+    const bool has = jf < je;
+    MP<L> xf = has ? ldm<L>(bs, a, i, jf) : mp_zero<L>();
+    const MP<L> uf = has ? ldm<L>(bs, a, c, jf) : mp_zero<L>();
+    if (tid == 0) {
         const MP<L> d = ldm<L>(bs, a, c, c);
         skip = is_zero<L>(d);
         if (!skip) {
@@ -146,14 +228,30 @@ k_lu_eliminate(Bases bs, MatRef a, int64_t c, int64_t je)
         }
     }
     __syncthreads();
-    if (skip) return;
-    MP<L> l;
+    if (!skip) {
+        MP<L> l;
 #pragma unroll
-    for (int q = 0; q < L; q++) l.m[q] = sl[q];
-    l.e = (int32_t)sl[L];
-    l.s = sl[L + 1];
-    for (int64_t j = c + 1 + threadIdx.x; j < je; j += ELIM_THREADS)
-        stm<L>(bs, a, i, j, sub_rn<L>(ldm<L>(bs, a, i, j), mul_rn<L>(l, ldm<L>(bs, a, c, j))));
+        for (int q = 0; q < L; q++) l.m[q] = sl[q];
+        l.e = (int32_t)sl[L];
+        l.s = sl[L + 1];
+        if (has) {
+            xf = sub_rn<L>(xf, mul_rn<L>(l, uf));
+            stm<L>(bs, a, i, jf, xf);
+        }
+        for (int64_t j = jf + ELIM_THREADS; j < je; j += ELIM_THREADS)
+            stm<L>(bs, a, i, j, sub_rn<L>(ldm<L>(bs, a, i, j), mul_rn<L>(l, ldm<L>(bs, a, c, j))));
+    }
+    // lane 0 now holds the row's final a_i,c+1 in xf (column c+1 < je)
+    if (next == ELIM_NEXT_DIAG) {
+        if (tid == 0 && i == c + 1) {
+            piv[c + 1] = (int32_t)(c + 1);
+            if (is_zero<L>(xf) && info[0] == 0) info[0] = (int32_t)(c + 2);
+        }
+        return;
+    }
+    if (next == ELIM_NEXT_KEYS && tid == 0)
+        keys[blockIdx.x] =
+            is_zero<L>(xf) ? 0ull : (((unsigned long long)(uint32_t)(xf.e + (1 << 30)) << 32) | xf.m[L - 1]);
 }
 
 // U12 := L11^-1 A12: one workgroup per column j >= je, one lane per panel row;
@@ -442,12 +540,26 @@ hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int
     return hipGetLastError();
 }
 
-hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, hipStream_t s)
+hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, int32_t* piv,
+                               int32_t* info, unsigned long long* keys, int next, hipStream_t s)
 {
     if (n - c - 1 <= 0) return hipSuccess;
-    if (L >= 64) return launch_lu_eliminate_wide(L, bs, a, n, c, je, s);
+    if (next != ELIM_PLAIN && (c + 1 >= je || (next == ELIM_NEXT_KEYS && !keys))) return hipErrorInvalidValue;
+    if (L >= 64) {
+        if (next != ELIM_PLAIN) return hipErrorInvalidValue;
+        return launch_lu_eliminate_wide(L, bs, a, n, c, je, s);
+    }
     MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_eliminate<LL>), dim3((unsigned)(n - c - 1)), dim3(ELIM_THREADS), 0, s,
-                                         bs, a, c, je));
+                                         bs, a, c, je, piv, info, keys, next));
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_pivot_keys(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                                int32_t* piv, int32_t* info, const unsigned long long* keys, hipStream_t s)
+{
+    if (L >= 64 || !keys || c >= n) return hipErrorInvalidValue;
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_pivot_keys<LL>), dim3(1), dim3(PIV_THREADS), 0, s, bs, a, n, c, j0, je,
+                                         piv, info, keys));
     return hipGetLastError();
 }
 

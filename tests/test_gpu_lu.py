@@ -5,6 +5,8 @@ same sequence of correctly rounded operations); residual and solution error
 are reported from the oracle's high-precision residual routine.
 """
 
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -63,6 +65,46 @@ def test_lu_zero_pivot_info():
     assert planes_equal(Fg, Fc)
 
 
+def test_lu_pivot_inside_panel_equal_keys_and_ties():
+    """Inside a panel the pivot of column c + 1 is settled by the elimination of
+    column c, from each row's 64-bit key (exponent, top limb) and a full
+    comparison of the rows holding the largest key.  Column 0 is e_0, so column
+    1 reaches that step unchanged: rows 5 and 130 hold 3/4, row 69 (the same
+    searching lane as row 5) holds 3/4 + 2^-200 (the same key, larger), row 100
+    holds -(3/4 + 2^-200) (equal magnitude, later index); every other row is
+    below 1/2.  The first index of the largest magnitude is row 69."""
+    p, n = 256, 150
+    A = I.uniform_pm1(n, n, p, 31)
+    zero, one = mpnum.from_int(0, p), mpnum.from_int(1, p)
+    I.set_entry(A, 0, 0, one, p)
+    for i in range(1, n):
+        I.set_entry(A, i, 0, zero, p)
+        half = mpnum.to_fraction(I.entry(A, i, 1, p), p) / 2
+        I.set_entry(A, i, 1, mpnum.from_fraction(half, p), p)
+    x = Fraction(3, 4)
+    y = x + Fraction(1, 1 << 200)
+    for i, v in ((5, x), (69, y), (100, -y), (130, x)):
+        I.set_entry(A, i, 1, mpnum.from_fraction(v, p), p)
+    Fc, pc, ic = cref.lu(A, p, panel=8, algo="winograd", cutoff=2)
+    assert pc[1] == 69
+    Fg, pg, ig = gpu_lu(A, p, 8, mp.WINOGRAD, 2)
+    assert ig == ic == 0
+    assert list(pg) == list(pc)
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+
+
+def test_lu_many_rows_per_pivot_step():
+    """n = 600 at 128 bits, panel 64: the pivot steps inside a panel read more
+    than 512 rows' keys (several chunks per searching lane)."""
+    p, n = 128, 600
+    A = I.uniform_pm1(n, n, p, 13)
+    Fc, pc, ic = cref.lu(A, p, panel=64, algo="winograd", cutoff=32)
+    Fg, pg, ig = gpu_lu(A, p, 64, mp.WINOGRAD, 32)
+    assert ig == ic == 0
+    assert list(pg) == list(pc)
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+
+
 @pytest.mark.parametrize("kind", ["random", "hilbert"])
 def test_lu_n512_p512_panel64_winograd(kind):
     """The LU workload: n = 512, 512 bits, panel 64, Winograd trailing
@@ -114,6 +156,21 @@ def test_lu_nopivot_zero_diagonal_skips_column():
     Fc, pc, ic = cref.lu(A, p, panel=4, algo="winograd", cutoff=1, pivot=False)
     Fg, pg, ig = gpu_lu_nopivot(A, p, 4, mp.WINOGRAD, 1)
     assert ig == ic == 1
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+
+
+def test_lu_nopivot_zero_diagonal_inside_panel():
+    """A zero pivot at the second column of a panel: l_10 = 0 leaves row 1
+    as it was, so a_11 = 0 reaches its step (info = 2, column skipped)."""
+    p, n = 256, 20
+    A = I.uniform_pm1(n, n, p, 8)
+    zero = mpnum.from_int(0, p)
+    I.set_entry(A, 1, 0, zero, p)
+    I.set_entry(A, 1, 1, zero, p)
+    Fc, pc, ic = cref.lu(A, p, panel=8, algo="winograd", cutoff=2, pivot=False)
+    Fg, pg, ig = gpu_lu_nopivot(A, p, 8, mp.WINOGRAD, 2)
+    assert ig == ic == 2
+    assert list(pg) == list(range(n))
     assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
 
 
