@@ -49,7 +49,9 @@ hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t k
 // piv[k0 .. k1) applied in order to the columns [c0, c1) and [c2, c3)
 hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1,
                            int64_t c0, int64_t c1, int64_t c2, int64_t c3, hipStream_t s);
-hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n,
+// luT: workspace of n * n * (L + 2) words for the transposed factors (the
+// one-workgroup solves below 2048 bits, n <= 4096); unused otherwise
+hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n, uint32_t* luT,
                            hipStream_t s);
 
 // the same operations for p = 2048, 4096, 8192, 10240 bits (L = 64, 128, 256,

@@ -163,7 +163,13 @@ int mp_lu_solve(int64_t n, int prec, const uint32_t* LU, int64_t lda, int64_t ps
     bs.p[BASE_B] = b;
     const MatRef lu{BASE_A, 0, 0, lda, psa};
     const MatRef x{BASE_B, 0, 0, 1, psb};
-    MPG_TRY(launch_lu_solve(L, bs, lu, x, piv, n, g_stream));
+    // the transposed factors for the one-workgroup solve (below 2048 bits)
+    uint32_t* luT = nullptr;
+    if (L < 64 && n <= 4096) {
+        luT = workspace((size_t)n * (size_t)n * (size_t)(L + 2), g_stream, WS_SOLVE, &rc);
+        if (rc) return rc;
+    }
+    MPG_TRY(launch_lu_solve(L, bs, lu, x, piv, n, luT, g_stream));
     return device_check();
 }
 

@@ -267,6 +267,8 @@ k_lu_u12(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
         __shared__ uint32_t su[L + 2];
         const int r = threadIdx.x;
         MP<L> x = r < kb ? ldm<L>(bs, a, j0 + r, j) : mp_zero<L>();
+        // l_r,t+1 is loaded while step t computes
+        MP<L> ln = (r > 0 && r < kb) ? ldm<L>(bs, a, j0 + r, j0) : mp_zero<L>();
         for (int64_t t = 0; t < kb - 1; t++) {
             if (r == t) {
 #pragma unroll
@@ -275,13 +277,15 @@ k_lu_u12(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
                 su[L + 1] = x.s;
             }
             __syncthreads();
+            const MP<L> lc = ln;
+            ln = (r > t + 1 && r < kb) ? ldm<L>(bs, a, j0 + r, j0 + t + 1) : mp_zero<L>();
             if (r > t && r < kb) {
                 MP<L> u;
 #pragma unroll
                 for (int q = 0; q < L; q++) u.m[q] = su[q];
                 u.e = (int32_t)su[L];
                 u.s = su[L + 1];
-                x = sub_rn<L>(x, mul_rn<L>(ldm<L>(bs, a, j0 + r, j0 + t), u));
+                x = sub_rn<L>(x, mul_rn<L>(lc, u));
             }
             __syncthreads();
         }
@@ -406,8 +410,26 @@ unsigned blocks_for(int64_t n, int per)
 
 }  // namespace
 
+// T := A^T for an n x n matrix, every plane: planes of T are n x n with
+// leading dimension n.  16 x 16 blocks go through LDS so that both the reads
+// and the writes of a wave are row segments.  Grid (blocks of columns, blocks
+// of rows, planes).
+__global__ void __launch_bounds__(256)
+k_lu_transpose(const uint32_t* __restrict__ A, int64_t lda, int64_t psa, uint32_t* __restrict__ T, int64_t n)
+{
+    __shared__ uint32_t tile[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t i0 = (int64_t)blockIdx.y * 16, j0 = (int64_t)blockIdx.x * 16, q = blockIdx.z;
+    if (i0 + ty < n && j0 + tx < n) tile[ty][tx] = A[q * psa + (i0 + ty) * lda + j0 + tx];
+    __syncthreads();
+    if (j0 + ty < n && i0 + tx < n) T[q * n * n + (j0 + ty) * n + i0 + tx] = tile[tx][ty];
+}
+
 // The same solve with the vector in registers: thread t owns rows t + k * 512
-// (k < RPT, n <= 512 RPT; 512 threads leave 256 registers per lane).  The row swaps are first composed into one
+// (k < RPT, n <= 512 RPT; 512 threads leave 256 registers per lane).  The
+// factors are read from their transpose luT (luT(j, i) = lu(i, j)), so the
+// column of L or U that a step needs is a run of consecutive words of every
+// plane: one workgroup streams the factors once, coalesced.  The row swaps are first composed into one
 // permutation in LDS; at every step the owner of the finished entry publishes
 // it through LDS (two alternating slots, one barrier per step) and every
 // other row applies its update in the same order as above.
@@ -415,7 +437,7 @@ constexpr int SOLVE_REG_THREADS = 512;
 
 template <int L, int RPT>
 __global__ void __launch_bounds__(SOLVE_REG_THREADS)
-k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
+k_lu_solve_reg(Bases bs, MatRef luT, MatRef x, const int32_t* piv, int64_t n)
 {
     __shared__ int32_t perm[SOLVE_REG_THREADS * RPT];
     __shared__ uint32_t sx[2][L + 2];
@@ -462,7 +484,7 @@ k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
 #pragma unroll
     for (int k = 0; k < RPT; k++) {
         const int r = tid + k * SOLVE_REG_THREADS;
-        fc[k] = (r > 0 && r < n) ? ldm<L>(bs, lu, r, 0) : mp_zero<L>();
+        fc[k] = (r > 0 && r < n) ? ldm<L>(bs, luT, 0, r) : mp_zero<L>();
     }
     for (int t = 0; t < (int)n; t++) {              // L y = P b, unit diagonal
         if (tid == t % SOLVE_REG_THREADS) {
@@ -476,7 +498,7 @@ k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
             const int r = tid + k * SOLVE_REG_THREADS;
-            fn[k] = (r > t + 1 && r < n) ? ldm<L>(bs, lu, r, t + 1) : mp_zero<L>();
+            fn[k] = (r > t + 1 && r < n) ? ldm<L>(bs, luT, t + 1, r) : mp_zero<L>();
         }
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
@@ -489,7 +511,7 @@ k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
 #pragma unroll
     for (int k = 0; k < RPT; k++) {
         const int r = tid + k * SOLVE_REG_THREADS;
-        fc[k] = r < n ? ldm<L>(bs, lu, r, n - 1) : mp_zero<L>();
+        fc[k] = r < n ? ldm<L>(bs, luT, n - 1, r) : mp_zero<L>();
     }
     for (int t = (int)n - 1; t >= 0; t--) {         // U x = y
         if (tid == t % SOLVE_REG_THREADS) {
@@ -506,7 +528,7 @@ k_lu_solve_reg(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
             const int r = tid + k * SOLVE_REG_THREADS;
-            fn[k] = (t >= 1 && r <= t - 1) ? ldm<L>(bs, lu, r, t - 1) : mp_zero<L>();
+            fn[k] = (t >= 1 && r <= t - 1) ? ldm<L>(bs, luT, t - 1, r) : mp_zero<L>();
         }
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
@@ -590,23 +612,32 @@ hipError_t launch_lu_laswp(int L, const Bases& bs, MatRef a, const int32_t* piv,
     return hipGetLastError();
 }
 
-hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n,
+hipError_t launch_lu_solve(int L, const Bases& bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n, uint32_t* luT,
                            hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (L >= 64) return launch_lu_solve_wide(L, bs, lu, x, piv, n, s);
-    const dim3 g(1), b(SOLVE_REG_THREADS);
-    if (n <= SOLVE_REG_THREADS) {
-        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 1>), g, b, 0, s, bs, lu, x, piv, n));
-    } else if (n <= 2 * SOLVE_REG_THREADS) {
-        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 2>), g, b, 0, s, bs, lu, x, piv, n));
-    } else if (n <= 4 * SOLVE_REG_THREADS) {
-        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 4>), g, b, 0, s, bs, lu, x, piv, n));
-    } else if (n <= 8 * SOLVE_REG_THREADS) {
-        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 8>), g, b, 0, s, bs, lu, x, piv, n));
-    } else {
-        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve<LL>), dim3(1), dim3(SOLVE_THREADS), 0, s, bs, lu, x, piv, n));
+    if (n <= 8 * SOLVE_REG_THREADS) {
+        if (!luT) return hipErrorInvalidValue;
+        const unsigned nb = (unsigned)((n + 15) / 16);
+        hipLaunchKernelGGL(k_lu_transpose, dim3(nb, nb, (unsigned)(L + 2)), dim3(256), 0, s,
+                           base_ptr(bs, lu.base) + lu.off, lu.ld, lu.ps, luT, n);
+        Bases bt = bs;
+        bt.p[BASE_C] = luT;
+        const MatRef t{BASE_C, 0, 0, n, n * n};
+        const dim3 g(1), b(SOLVE_REG_THREADS);
+        if (n <= SOLVE_REG_THREADS) {
+            MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 1>), g, b, 0, s, bt, t, x, piv, n));
+        } else if (n <= 2 * SOLVE_REG_THREADS) {
+            MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 2>), g, b, 0, s, bt, t, x, piv, n));
+        } else if (n <= 4 * SOLVE_REG_THREADS) {
+            MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 4>), g, b, 0, s, bt, t, x, piv, n));
+        } else {
+            MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve_reg<LL, 8>), g, b, 0, s, bt, t, x, piv, n));
+        }
+        return hipGetLastError();
     }
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_solve<LL>), dim3(1), dim3(SOLVE_THREADS), 0, s, bs, lu, x, piv, n));
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ int check_prec(int prec, int* L);
 int check_mat(const char* name, const uint32_t* p, int64_t rows, int64_t cols, int64_t ld, int64_t ps);
 bool overlaps(const uint32_t* a, int64_t psa, const uint32_t* b, int64_t psb, int L);
 int device_check();
-enum WsSlot { WS_PLAN = 0, WS_LU = 1, WS_SLICE = 2, WS_SLICE_EXP = 3, WS_BATCH = 4 };
+enum WsSlot { WS_PLAN = 0, WS_LU = 1, WS_SLICE = 2, WS_SLICE_EXP = 3, WS_BATCH = 4, WS_SOLVE = 5 };
 // per-stream, per-slot device buffer of at least `words` uint32 (grown on demand)
 uint32_t* workspace(size_t words, hipStream_t s, int slot, int* rc);
 

@@ -103,6 +103,9 @@ def test_lu_many_rows_per_pivot_step():
     assert ig == ic == 0
     assert list(pg) == list(pc)
     assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+    # the solve with two rows per thread (n > 512)
+    b = cref.gemm(A, I.ones_column(n, p), p, algo="simple")
+    assert planes_equal(gpu_solve(Fg, pg, b, p), cref.lu_solve(Fc, pc, b, p))
 
 
 @pytest.mark.parametrize("kind", ["random", "hilbert"])
