@@ -161,45 +161,77 @@ k_lu_pivot_swap_w(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t 
     __syncthreads();
     const int64_t r = s_r;
     if (r != c) {
+        // words e = q wd + (j - j0) of the two rows, SW per thread per round,
+        // all loads of a round before any store (the rows never overlap)
+        constexpr int SW = 16;
         uint32_t* p = base_ptr(bs, a.base) + a.off;
-        const int64_t wd = je - j0;
-        for (int64_t e = threadIdx.x; e < wd * (L + 2); e += WT) {
-            const int64_t j = j0 + e % wd, q = e / wd;
-            uint32_t* x = p + q * a.ps + c * a.ld + j;
-            uint32_t* y = p + q * a.ps + r * a.ld + j;
-            const uint32_t tmp = *x;
-            *x = *y;
-            *y = tmp;
+        const uint32_t wd = (uint32_t)(je - j0), tot = wd * (uint32_t)(L + 2);
+        uint32_t* rc = p + c * a.ld + j0;
+        uint32_t* rr = p + r * a.ld + j0;
+        for (uint32_t e0 = 0; e0 < tot; e0 += SW * WT) {
+            uint32_t xv[SW], yv[SW];
+            int64_t off[SW];
+#pragma unroll
+            for (int u = 0; u < SW; u++) {
+                const uint32_t e = e0 + (uint32_t)(u * WT) + threadIdx.x;
+                off[u] = e < tot ? (int64_t)(e / wd) * a.ps + (e % wd) : -1;
+                if (off[u] >= 0) {
+                    xv[u] = rc[off[u]];
+                    yv[u] = rr[off[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SW; u++) {
+                if (off[u] >= 0) {
+                    rc[off[u]] = yv[u];
+                    rr[off[u]] = xv[u];
+                }
+            }
         }
     }
 }
 
-// one wave per row i in (c, n): l = a_ic / a_cc, then a_ij := a_ij - l a_cj for
-// the panel columns j in (c, je); a zero pivot skips the column
+// one wave per row i in (c, n): the multiplier l_i = a_ic / a_cc replaces a_ic;
+// a zero pivot skips the column (no quotient, no update)
 template <int L>
 __global__ void __launch_bounds__(64)
-k_lu_eliminate_w(Bases bs, MatRef a, int64_t c, int64_t je)
+k_lu_div_col_w(Bases bs, MatRef a, int64_t c)
 {
     const int64_t i = c + 1 + blockIdx.x;
     const WMP<L> d = wld<L>(bs, a, c, c);
     if (wis_zero<L>(d)) return;
-    const WMP<L> l = div_rn<L>(wld<L>(bs, a, i, c), d);
-    wst<L>(bs, a, i, c, l);
-    for (int64_t j = c + 1; j < je; j++) wst<L>(bs, a, i, j, sub_rn<L>(wld<L>(bs, a, i, j), mul_rn<L>(l, wld<L>(bs, a, c, j))));
+    wst<L>(bs, a, i, c, div_rn<L>(wld<L>(bs, a, i, c), d));
 }
 
-// U12 := L11^-1 A12, one workgroup per column j >= je: step t updates the rows
-// r > t of the panel with row t (rows split over the waves, a barrier between
-// steps), the same order as the one-value-per-lane kernel
+// a_ij := a_ij - l_i a_cj for the rows i in (c, n) and the panel columns j in
+// (c, je), one wave per element; l_i is a_ic, which k_lu_div_col_w has just
+// made the multiplier (nothing to do after a zero pivot)
 template <int L>
 __global__ void __launch_bounds__(WT)
+k_lu_rank1_w(Bases bs, MatRef a, int64_t n, int64_t c, int64_t je)
+{
+    const int64_t wj = je - c - 1;
+    const int64_t e = (int64_t)blockIdx.x * WW + wave_id();
+    if (e >= (n - c - 1) * wj) return;
+    const int64_t i = c + 1 + e / wj, j = c + 1 + e % wj;
+    if (wis_zero<L>(wld<L>(bs, a, c, c))) return;
+    wst<L>(bs, a, i, j, sub_rn<L>(wld<L>(bs, a, i, j), mul_rn<L>(wld<L>(bs, a, i, c), wld<L>(bs, a, c, j))));
+}
+
+// U12 := L11^-1 A12, one workgroup of WU / 64 waves per column j >= je: step t
+// updates the rows r > t of the panel with row t (rows split over the waves, a
+// barrier between steps), the same order as the one-value-per-lane kernel
+constexpr int WU = 512;
+
+template <int L>
+__global__ void __launch_bounds__(WU)
 k_lu_u12_w(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
 {
     const int64_t j = je + blockIdx.x;
     const int w = wave_id();
     for (int64_t t = 0; t < kb - 1; t++) {
         const WMP<L> u = wld<L>(bs, a, j0 + t, j);
-        for (int64_t r = t + 1 + w; r < kb; r += WW)
+        for (int64_t r = t + 1 + w; r < kb; r += WU / 64)
             wst<L>(bs, a, j0 + r, j, sub_rn<L>(wld<L>(bs, a, j0 + r, j), mul_rn<L>(wld<L>(bs, a, j0 + r, j0 + t), u)));
         __syncthreads();
     }
@@ -207,37 +239,55 @@ k_lu_u12_w(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
 
 // x := U^-1 L^-1 P b in one workgroup of 16 waves (the vector in global
 // memory, a barrier between steps)
-constexpr int WSOLVE = 1024, WSW = WSOLVE / 64;
+// The solve, one launch per step so that every row has its own wave on any CU
+// (one workgroup would give each of its 16 waves n / 16 rows per step):
+// k_lu_solve_perm_w applies the row exchanges to b in order (one wave);
+// k_lu_fwd_w (step t of L y = P b, unit diagonal) updates the rows r > t with
+// the finished y_t; k_lu_div_w finishes x_(n-1) = y_(n-1) / u_(n-1,n-1);
+// k_lu_bwd_w (step t of U x = y) updates the rows r < t with the finished
+// x_t, and the wave of row t - 1, whose update was its last, divides it by
+// u_(t-1,t-1) so that the next step finds it finished.  Every element sees
+// the operations of the one-workgroup solve in the same order.
+template <int L>
+__global__ void __launch_bounds__(64)
+k_lu_solve_perm_w(Bases bs, MatRef x, const int32_t* piv, int64_t n)
+{
+    for (int64_t k = 0; k < n; k++) {
+        const int64_t r = piv[k];
+        if (r == k) continue;
+        const WMP<L> u = wld<L>(bs, x, k, 0), v = wld<L>(bs, x, r, 0);
+        wst<L>(bs, x, k, 0, v);
+        wst<L>(bs, x, r, 0, u);
+    }
+}
 
 template <int L>
-__global__ void __launch_bounds__(WSOLVE)
-k_lu_solve_w(Bases bs, MatRef lu, MatRef x, const int32_t* piv, int64_t n)
+__global__ void __launch_bounds__(WT)
+k_lu_fwd_w(Bases bs, MatRef lu, MatRef x, int64_t n, int64_t t)
 {
-    const int w = wave_id();
-    if (w == 0) {
-        for (int64_t k = 0; k < n; k++) {
-            const int64_t r = piv[k];
-            if (r == k) continue;
-            const WMP<L> u = wld<L>(bs, x, k, 0), v = wld<L>(bs, x, r, 0);
-            wst<L>(bs, x, k, 0, v);
-            wst<L>(bs, x, r, 0, u);
-        }
-    }
-    __syncthreads();
-    for (int64_t t = 0; t < n; t++) {                 // L y = P b, unit diagonal
-        const WMP<L> yt = wld<L>(bs, x, t, 0);
-        for (int64_t r = t + 1 + w; r < n; r += WSW)
-            wst<L>(bs, x, r, 0, sub_rn<L>(wld<L>(bs, x, r, 0), mul_rn<L>(wld<L>(bs, lu, r, t), yt)));
-        __syncthreads();
-    }
-    for (int64_t t = n - 1; t >= 0; t--) {            // U x = y
-        if (w == 0) wst<L>(bs, x, t, 0, div_rn<L>(wld<L>(bs, x, t, 0), wld<L>(bs, lu, t, t)));
-        __syncthreads();
-        const WMP<L> xt = wld<L>(bs, x, t, 0);
-        for (int64_t r = w; r < t; r += WSW)
-            wst<L>(bs, x, r, 0, sub_rn<L>(wld<L>(bs, x, r, 0), mul_rn<L>(wld<L>(bs, lu, r, t), xt)));
-        __syncthreads();
-    }
+    const int64_t r = t + 1 + (int64_t)blockIdx.x * WW + wave_id();
+    if (r >= n) return;
+    const WMP<L> yt = wld<L>(bs, x, t, 0);
+    wst<L>(bs, x, r, 0, sub_rn<L>(wld<L>(bs, x, r, 0), mul_rn<L>(wld<L>(bs, lu, r, t), yt)));
+}
+
+template <int L>
+__global__ void __launch_bounds__(64)
+k_lu_div_w(Bases bs, MatRef lu, MatRef x, int64_t t)
+{
+    wst<L>(bs, x, t, 0, div_rn<L>(wld<L>(bs, x, t, 0), wld<L>(bs, lu, t, t)));
+}
+
+template <int L>
+__global__ void __launch_bounds__(WT)
+k_lu_bwd_w(Bases bs, MatRef lu, MatRef x, int64_t t)
+{
+    const int64_t r = (int64_t)blockIdx.x * WW + wave_id();
+    if (r >= t) return;
+    const WMP<L> xt = wld<L>(bs, x, t, 0);
+    WMP<L> v = sub_rn<L>(wld<L>(bs, x, r, 0), mul_rn<L>(wld<L>(bs, lu, r, t), xt));
+    if (r == t - 1) v = div_rn<L>(v, wld<L>(bs, lu, r, r));
+    wst<L>(bs, x, r, 0, v);
 }
 
 }  // namespace
@@ -310,8 +360,15 @@ hipError_t launch_lu_eliminate_wide(int L, const Bases& bs, MatRef a, int64_t n,
                                     hipStream_t s)
 {
     if (n - c - 1 <= 0) return hipSuccess;
-    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_eliminate_w<LL>), dim3((unsigned)(n - c - 1)), dim3(64), 0, s, bs,
-                                            a, c, je));
+    // the multipliers (one wave per row), then the rank-one update of the
+    // panel (one wave per element)
+    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_div_col_w<LL>), dim3((unsigned)(n - c - 1)), dim3(64), 0, s, bs,
+                                            a, c));
+    const int64_t cnt = (n - c - 1) * (je - c - 1);
+    if (cnt > 0) {
+        const unsigned g = (unsigned)((cnt + WW - 1) / WW);
+        MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_rank1_w<LL>), dim3(g), dim3(WT), 0, s, bs, a, n, c, je));
+    }
     return hipGetLastError();
 }
 
@@ -319,7 +376,7 @@ hipError_t launch_lu_u12_wide(int L, const Bases& bs, MatRef a, int64_t j0, int6
                               hipStream_t s)
 {
     if (n - je <= 0 || kb <= 1) return hipSuccess;
-    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_u12_w<LL>), dim3((unsigned)(n - je)), dim3(WT), 0, s, bs, a, j0,
+    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_u12_w<LL>), dim3((unsigned)(n - je)), dim3(WU), 0, s, bs, a, j0,
                                             kb, je));
     return hipGetLastError();
 }
@@ -328,7 +385,16 @@ hipError_t launch_lu_solve_wide(int L, const Bases& bs, MatRef lu, MatRef x, con
                                 hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_solve_w<LL>), dim3(1), dim3(WSOLVE), 0, s, bs, lu, x, piv, n));
+    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_solve_perm_w<LL>), dim3(1), dim3(64), 0, s, bs, x, piv, n));
+    for (int64_t t = 0; t + 1 < n; t++) {
+        const unsigned g = (unsigned)((n - t - 1 + WW - 1) / WW);
+        MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_fwd_w<LL>), dim3(g), dim3(WT), 0, s, bs, lu, x, n, t));
+    }
+    MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_div_w<LL>), dim3(1), dim3(64), 0, s, bs, lu, x, n - 1));
+    for (int64_t t = n - 1; t >= 1; t--) {
+        const unsigned g = (unsigned)((t + WW - 1) / WW);
+        MPG_DISPATCH_WIDE(L, hipLaunchKernelGGL((k_lu_bwd_w<LL>), dim3(g), dim3(WT), 0, s, bs, lu, x, t));
+    }
     return hipGetLastError();
 }
 
