@@ -133,11 +133,12 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
 
 // The pivot of column c when the elimination of column c - 1 has left each
 // row's 64-bit key (exponent, top limb; 0 for zero) in keys[i - c] for the
-// rows i in [c, n): the keys are read coalesced, KR per thread at a time, the
-// largest is found in LDS, and only the rows holding it have their values
-// read and compared in full (ascending, first index on ties); then the pivot
-// is settled and rows c and r exchanged over the panel columns [j0, je) as by
-// the full search.
+// rows i in [c, n): the keys are read coalesced, KR per thread at a time, and
+// the largest is found in LDS.  When one row holds it, that row is the pivot
+// (a nonzero key is a nonzero value); otherwise only the rows holding it have
+// their values read and compared in full (ascending, first index on ties) and
+// the pivot is settled as by the full search (a zero column: the first row,
+// info).  Then rows c and r are exchanged over the panel columns [j0, je).
 template <int L>
 __global__ void __launch_bounds__(PIV_THREADS)
 k_lu_pivot_keys(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info,
@@ -163,8 +164,13 @@ k_lu_pivot_keys(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
     atomicMax(&smax, km);
     __syncthreads();
     const unsigned long long kmax = smax;
-    int32_t best = -1;
-    MP<L> bv = mp_zero<L>();
+    // the rows holding kmax: counted, and the smallest index kept
+    __shared__ int32_t scnt, sfirst;
+    if (tid == 0) {
+        scnt = 0;
+        sfirst = INT32_MAX;
+    }
+    __syncthreads();
     for (int64_t k0 = 0; k0 < m; k0 += KR * NT) {
         unsigned long long kr[KR];
 #pragma unroll
@@ -176,15 +182,42 @@ k_lu_pivot_keys(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
         for (int u = 0; u < KR; u++) {
             const int64_t k = k0 + u * NT + tid;
             if (k < m && kr[u] == kmax) {
-                const MP<L> v = ldm<L>(bs, a, c + k, c);
-                if (best < 0 || cmp_abs<L>(v, bv) > 0) {
-                    best = (int32_t)(c + k);
-                    bv = v;
-                }
+                atomicAdd(&scnt, 1);
+                atomicMin(&sfirst, (int32_t)k);
             }
         }
     }
-    const int64_t r = settle_pivot<L, NT>(best, bv, c, piv, info);
+    __syncthreads();
+    int64_t r;
+    if (scnt == 1 && kmax != 0) {
+        // one row holds the largest key: it is the pivot, and nonzero
+        r = c + sfirst;
+        if (tid == 0) piv[c] = (int32_t)r;
+    } else {
+        // equal keys (or a zero column): compare the full values of those rows
+        int32_t best = -1;
+        MP<L> bv = mp_zero<L>();
+        for (int64_t k0 = 0; k0 < m; k0 += KR * NT) {
+            unsigned long long kr[KR];
+#pragma unroll
+            for (int u = 0; u < KR; u++) {
+                const int64_t k = k0 + u * NT + tid;
+                kr[u] = k < m ? keys[k] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < KR; u++) {
+                const int64_t k = k0 + u * NT + tid;
+                if (k < m && kr[u] == kmax) {
+                    const MP<L> v = ldm<L>(bs, a, c + k, c);
+                    if (best < 0 || cmp_abs<L>(v, bv) > 0) {
+                        best = (int32_t)(c + k);
+                        bv = v;
+                    }
+                }
+            }
+        }
+        r = settle_pivot<L, NT>(best, bv, c, piv, info);
+    }
     if (r != c) swap_rows<L, NT>(bs, a, c, r, j0, je);
 }
 
@@ -216,10 +249,10 @@ k_lu_eliminate(Bases bs, MatRef a, int64_t c, int64_t je, int32_t* piv, int32_t*
     MP<L> xf = has ? ldm<L>(bs, a, i, jf) : mp_zero<L>();
     const MP<L> uf = has ? ldm<L>(bs, a, c, jf) : mp_zero<L>();
     if (tid == 0) {
-        const MP<L> d = ldm<L>(bs, a, c, c);
+        const MP<L> d = ldm<L>(bs, a, c, c), x = ldm<L>(bs, a, i, c);    // both loads in flight
         skip = is_zero<L>(d);
         if (!skip) {
-            const MP<L> l = div_rn<L>(ldm<L>(bs, a, i, c), d);
+            const MP<L> l = div_rn<L>(x, d);
             stm<L>(bs, a, i, c, l);
 #pragma unroll
             for (int q = 0; q < L; q++) sl[q] = l.m[q];
