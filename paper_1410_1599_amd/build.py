@@ -36,9 +36,16 @@ def headers():
     return hs
 
 
+# the product at 1024 bits is a fully unrolled 32 x 32-limb column loop; under
+# the default threshold the compiler leaves it rolled and indexes the limbs
+# through a stack array (scratch memory)
+UNROLL = ["-mllvm", "-pragma-unroll-threshold=500000"]
+EXTRA_FLAGS = {"gemm_kernels.hip": UNROLL, "lu_kernels.hip": UNROLL}
+
+
 def _compile(src):
     obj = os.path.join(OUT, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + HIP_FLAGS + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-x", "hip"] + HIP_FLAGS + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
