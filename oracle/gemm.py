@@ -7,7 +7,7 @@ oracle.mpnum.  Every scalar operation rounds once (mpnum.mul, mpnum.add,
 mpnum.sub), so Strassen and Winograd reach a *different* rounded result from
 Simple; the functions below fix the order of every operation.
 
-Readings of the paper used here (each is listed in the design doc):
+Readings of the paper used here:
 
 * Simple, eq. (1): c_ij starts at exact zero and takes add(c_ij,
   mul(a_ik, b_kj)) for k ascending (a product is rounded, then the sum is

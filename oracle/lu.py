@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see oracle/mpnum.py).
 Section 4 factors A in blocks of K columns: A11 = L11 U11, A12 -> U12,
 A21 -> L21, then A22 := A22 - L21 U12 with the product formed by one of the
 matrix-multiplication algorithms, and repeats on A22.  The paper's LU does
-not pivot; this one adds row partial pivoting (readings listed in the design doc):
+not pivot; this one adds row partial pivoting, with these readings:
 
 * pivot row = the smallest index i >= c that maximises |a_ic| (exact
   comparison);
