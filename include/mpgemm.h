@@ -137,8 +137,10 @@ int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, 
  * launch, and every leaf product of every item shares one launch (the
  * paper's seven sub-products per level and many uneven products issued
  * together).  Each C_r is bit-identical to mp_gemm of that item alone.
- * Results must not overlap one another or any operand.  Items with m or n
- * zero are skipped.  Odd sizes and leaf kernel follow mp_set_policy.
+ * Results must not overlap one another or any operand of any item
+ * (MP_E_ALIAS, checked over all items before anything is launched); operands
+ * may share memory.  Items with m or n zero are skipped.  Odd sizes and leaf
+ * kernel follow mp_set_policy.
  */
 int mp_gemm_batched(int count, const int64_t *m, const int64_t *l, const int64_t *n, int prec, int algo, int cutoff,
                     const uint32_t *const *A, const int64_t *lda, const int64_t *psa,
@@ -187,7 +189,9 @@ int mp_plan_info(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff
  * bits at or above 2^(e_i - W_A) (2^(f_j - W_B)): its truncation error is below
  * that power of two.  window_out (host, 2 int32, may be NULL) gets
  * W_A, W_B.  Synchronises the stream (the window depends on the data).
- * prec 128 .. 1024 only (MP_E_PREC above).
+ * prec 128 .. 1024 only (MP_E_PREC above); inner size l <= 131008 (MP_E_RANGE
+ * above: the INT32 digit sums and the 64-bit recombination are exact only
+ * up to there).
  */
 int mp_gemm_slice(int64_t m, int64_t l, int64_t n, int prec, int extra,
                   const uint32_t *A, int64_t lda, int64_t psa,

@@ -63,8 +63,16 @@ def build(force=True, jobs=None, verbose=False):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= newest_input:
         return LIB
     jobs = jobs or min(8, len(srcs))
+    newest_header = max(os.path.getmtime(p) for p in headers() + [__file__])
+
+    def fresh(src):                     # incremental builds reuse objects newer than every input
+        obj = os.path.join(OUT, os.path.basename(src) + ".o")
+        return (not force and os.path.exists(obj)
+                and os.path.getmtime(obj) >= max(os.path.getmtime(src), newest_header))
+
     with cf.ThreadPoolExecutor(jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda src: (os.path.join(OUT, os.path.basename(src) + ".o"), "") if fresh(src)
+                              else _compile(src), srcs))
     for _, msgs in results:
         if verbose and msgs.strip():
             print(msgs)

@@ -8,6 +8,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <cstdio>
 #include <map>
@@ -566,17 +567,36 @@ int mp_gemm_batched(int count, const int64_t* m, const int64_t* l, const int64_t
             (rc = check_mat("C", C[r], m[r], n[r], ldc[r], psc[r])))
             return rc;
         if (m[r] == 0 || n[r] == 0) continue;
-        if (l[r] > 0 && (overlaps(C[r], psc[r], A[r], psa[r], L) || overlaps(C[r], psc[r], B[r], psb[r], L)))
-            return set_err(MP_E_ALIAS, "C overlaps A or B");
-        for (size_t q = 0; q < table.size(); q += 3)
-            if (overlaps(C[r], psc[r], table[q + 2], items[q / 3].psc, L))
-                return set_err(MP_E_ALIAS, "two results of the batch overlap");
         items.push_back(BatchItem{m[r], l[r], n[r], lda[r], psa[r], ldb[r], psb[r], ldc[r], psc[r]});
         table.push_back(const_cast<uint32_t*>(A[r]));
         table.push_back(const_cast<uint32_t*>(B[r]));
         table.push_back(C[r]);
     }
     if (items.empty()) return MP_OK;
+    // every leaf of every item runs in one grouped launch, so no result may
+    // overlap any operand or result of any item (inputs may share memory)
+    {
+        struct Extent { uintptr_t lo, hi; bool out; };
+        std::vector<Extent> ext;
+        for (size_t q = 0; q < items.size(); q++) {
+            auto add = [&](const uint32_t* p, int64_t ps, bool out) {
+                const uintptr_t lo = (uintptr_t)p, hi = lo + 4ull * (uint64_t)(L + 2) * (uint64_t)ps;
+                if (hi > lo) ext.push_back(Extent{lo, hi, out});
+            };
+            if (items[q].l > 0) {
+                add(table[3 * q], items[q].psa, false);
+                add(table[3 * q + 1], items[q].psb, false);
+            }
+            add(table[3 * q + 2], items[q].psc, true);
+        }
+        std::sort(ext.begin(), ext.end(), [](const Extent& a, const Extent& b) { return a.lo < b.lo; });
+        uintptr_t end_in = 0, end_out = 0;           // largest end so far of inputs / of results
+        for (const Extent& e : ext) {
+            if (e.lo < end_out || (e.out && e.lo < end_in))
+                return set_err(MP_E_ALIAS, "a result of the batch overlaps an operand or another result");
+            (e.out ? end_out : end_in) = std::max(e.out ? end_out : end_in, e.hi);
+        }
+    }
     if ((rc = device_check())) return rc;
     hipStream_t s = g_stream;
     Plan P;

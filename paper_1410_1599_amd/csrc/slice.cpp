@@ -225,6 +225,10 @@ extern "C" int mp_gemm_slice(int64_t m, int64_t l, int64_t n, int prec, int extr
     if (L > 32) return set_err(MP_E_PREC, "the slice path takes prec 128 .. 1024");
     if (extra < 0 || extra > SLICE_MAX_EXTRA) return set_err(MP_E_ARG, "extra must be in 0..64");
     if (m < 0 || l < 0 || n < 0) return set_err(MP_E_ARG, "negative dimension");
+    // one digit-pair GEMM sums up to l products of at most 2^14 in INT32, and
+    // the recombination's 64-bit partial sums stay exact while
+    // min(S_A, S_B) * l < 2^25 (S <= 137 digits at 1024 bits)
+    if (l > SLICE_KMAX) return set_err(MP_E_RANGE, "the slice path takes inner sizes l <= 131008");
     if ((rc = check_mat("A", A, m, l, lda, psa)) || (rc = check_mat("B", B, l, n, ldb, psb)) ||
         (rc = check_mat("C", C, m, n, ldc, psc)))
         return rc;

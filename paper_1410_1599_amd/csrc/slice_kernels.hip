@@ -378,8 +378,11 @@ k_slice_gemm(const SliceTask* __restrict__ tasks, const int8_t* __restrict__ A8,
 
 // c_ij = RN_p(2^(e_i + f_j - W_A - W_B) * Z), Z = sum_u 256^u G_u,ij.
 // slot_begin[u] .. slot_begin[u+1] are the G slots of diagonal u.  The sum is
-// kept as signed 64-bit partial sums per 32-bit position (each below 2^58),
-// carried once.
+// kept as signed 64-bit partial sums per 32-bit position, carried once: the
+// partial sum of position q takes diagonals 4q .. 4q+3, each at most
+// min(S_A, S_B) l 2^14 in magnitude, shifted by at most 24 bits, so it stays
+// below min(S_A, S_B) l 2^38 (1 + 2^-8 + 2^-16 + 2^-24) < 2^63 for
+// min(S_A, S_B) l < 2^25, which the host guarantees (l <= 131008, S <= 137).
 //
 // mode 0: every diagonal.  mode 1: only the diagonals u >= ulo (the first pass
 // of the certified early stop); the omitted part is below 2^D in magnitude, so

@@ -107,3 +107,52 @@ def test_argument_errors_without_device(mp):
     info = ctypes.c_int(0)
     assert lib.mp_lu_ex(4, 256, fake, 4, 16, fake, ctypes.byref(info), 0, 3, 32, 0) == -1   # panel 0
     assert lib.mp_lu_ex(4, 200, fake, 4, 16, fake, ctypes.byref(info), 64, 3, 32, 0) == -2
+
+
+def test_batched_alias_across_items_without_device(mp):
+    """A result of one item overlapping an operand or result of another item is
+    rejected (all leaves of a batch run in one launch); disjoint buffers and
+    operands shared between items pass validation (the call then needs the
+    device, which a CPU host does not have: MP_E_DEVICE or MP_OK, never
+    MP_E_ALIAS)."""
+    lib = mp.lib
+    L = 256 // 32
+    words = (L + 2) * 16            # one 4 x 4 matrix
+
+    def batch(ptrs):
+        cnt = len(ptrs)
+        i64 = ctypes.c_int64 * cnt
+        vp = ctypes.c_void_p * cnt
+        four = i64(*([4] * cnt))
+        sixteen = i64(*([16] * cnt))
+        A = vp(*[ctypes.c_void_p(a) for a, _, _ in ptrs])
+        B = vp(*[ctypes.c_void_p(b) for _, b, _ in ptrs])
+        C = vp(*[ctypes.c_void_p(c) for _, _, c in ptrs])
+        return lib.mp_gemm_batched(cnt, four, four, four, 256, 0, 0, A, four, sixteen, B, four, sixteen,
+                                   C, four, sixteen)
+
+    base = 1 << 40
+    at = lambda k: base + 4 * words * k
+    # item 1's result is item 0's A
+    assert batch([(at(0), at(1), at(2)), (at(3), at(4), at(0))]) == -3
+    # item 0's result overlaps item 1's B by one word
+    assert batch([(at(0), at(1), at(2)), (at(3), at(2) + 4 * words - 4, at(5))]) == -3
+    # two results overlap
+    assert batch([(at(0), at(1), at(2)), (at(3), at(4), at(2) + 4)]) == -3
+    # shared operands, disjoint results: not an alias error
+    assert batch([(at(0), at(1), at(2)), (at(0), at(1), at(3))]) != -3
+
+
+def test_slice_inner_size_limit_without_device(mp):
+    lib = mp.lib
+    l = 131009
+    base = 1 << 40
+    L = 256 // 32
+    A = base
+    B = base + 4 * (L + 2) * 4 * l + (1 << 20)
+    C = B + 4 * (L + 2) * 4 * l + (1 << 20)
+    w = (ctypes.c_int * 2)()
+    rc = lib.mp_gemm_slice(4, l, 4, 256, 64, ctypes.c_void_p(A), l, 4 * l, ctypes.c_void_p(B), 4, 4 * l,
+                           ctypes.c_void_p(C), 4, 16, w)
+    assert rc == -6, rc
+    assert "131008" in mp.last_error()

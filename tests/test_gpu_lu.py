@@ -193,3 +193,21 @@ def test_lu_nopivot_n512_lotkin_and_solve():
     assert planes_equal(xg, cref.lu_solve(Fc, pc, b, p))
     err = max(abs(mpnum.to_fraction(I.entry(xg, i, 0, p), p) - i) for i in range(n))
     print("Lotkin n=512, 512 bits, unpivoted: max |x - x_true| = %.3g" % float(err))
+
+
+@pytest.mark.parametrize("kind", ["random", "hilbert"])
+def test_bench_residual_matches_oracle(kind):
+    """The benchmark evaluates ||PA - LU||_inf / ||A||_inf on the GPU at 2p bits;
+    it must agree with the C oracle's high-precision residual of the same
+    factors (to well under a bit of the ratio)."""
+    import bench
+    p, n = 256, 96
+    A = I.uniform_pm1(n, n, p, 5) if kind == "random" else I.hilbert(n, p)
+    dA = mp.to_device(A)
+    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    mp.mp_lu_ex(n, p, dA, piv, 32, mp.WINOGRAD, 8)
+    torch.cuda.synchronize()
+    l2_gpu, _ = bench.lu_residual_2p(mp, torch, A, dA, piv, p)
+    l2_ref, _ = cref.lu_residual(A, mp.to_host(dA), piv.cpu().numpy(), p)
+    assert abs(l2_gpu - l2_ref) < 0.01, (l2_gpu, l2_ref)
+    assert l2_ref < -p + 20
