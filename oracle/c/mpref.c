@@ -26,7 +26,9 @@
 #include <string.h>
 #include <math.h>
 
-#define MAXL 48              /* up to 1536 bits (the residual runs at 2p+64) */
+#ifndef MAXL
+#define MAXL 48              /* up to 1536 bits (the residual runs at 2p+64); the wide build sets 656 */
+#endif
 #define WIDE (2 * MAXL + 8)
 
 typedef struct {
