@@ -123,6 +123,26 @@ int mp_gemm(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff,
             const uint32_t *B, int64_t ldb, int64_t psb,
             uint32_t *C, int64_t ldc, int64_t psc);
 
+/*
+ * mp_gemm without any device allocation, for callers that cannot allocate
+ * (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks, policy and leaf settings, kernels and
+ * result bits as mp_gemm; the caller passes A, B and C as there.  The plan's
+ * task arrays and every temporary of the recursion live in one device array
+ * of the library, 256 MiB per GPU, held from the library's load until the
+ * process ends; a product needing more (mp_plan_info's ws_bytes plus its task
+ * arrays: e.g. Winograd at cutoff 64 to n = 512 at 128 bits, n = 256 at 512
+ * bits; Simple and Block at any size) returns MP_E_RANGE before anything is
+ * launched.  Calls on one GPU share that array: calls that overlap in time on
+ * one GPU (different streams or threads) race and must be ordered by the
+ * caller; calls in one stream are ordered by it.  Nothing in the array needs
+ * to start at zero.  Asynchronous on the stream of mp_set_stream.
+ */
+int mp_gemm_noalloc(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff,
+                    const uint32_t *A, int64_t lda, int64_t psa,
+                    const uint32_t *B, int64_t ldb, int64_t psb,
+                    uint32_t *C, int64_t ldc, int64_t psc);
+
 /* mp_gemm with an explicit odd-size policy (enum mp_policy) and leaf kernel (enum mp_leaf). */
 int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, int policy, int leaf,
                const uint32_t *A, int64_t lda, int64_t psa,

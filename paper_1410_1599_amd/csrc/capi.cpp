@@ -84,6 +84,7 @@ void free_plan_device(Plan& P)
     P.d_gemm = nullptr;
     P.d_node = nullptr;
     P.d_tiles = nullptr;
+    P.on_device = false;
 }
 
 template <class T>
@@ -150,26 +151,36 @@ int device_check()
     return MP_OK;
 }
 
-Plan* get_plan(const PlanKey& key, int* rc)
+Plan* get_plan(const PlanKey& key, int* rc, bool device)
 {
     DeviceState& S = dev_state();
     std::lock_guard<std::mutex> g(S.mu);
+    Plan* raw;
     auto it = S.plans.find(key);
-    if (it != S.plans.end()) return it->second.get();
-    std::unique_ptr<Plan> P(new Plan());
-    build_plan(*P, key);
-    const char* why = nullptr;
-    if (!validate_plan(*P, &why)) {
-        *rc = set_err(MP_E_ARG, why);      // a planner defect: refuse rather than launch
-        return nullptr;
+    if (it != S.plans.end()) {
+        raw = it->second.get();
+    } else {
+        std::unique_ptr<Plan> P(new Plan());
+        build_plan(*P, key);
+        const char* why = nullptr;
+        if (!validate_plan(*P, &why)) {
+            *rc = set_err(MP_E_ARG, why);      // a planner defect: refuse rather than launch
+            return nullptr;
+        }
+        raw = P.get();
+        S.plans[key] = std::move(P);
     }
-    if ((*rc = upload(&P->d_gemm, P->gemm)) || (*rc = upload(&P->d_node, P->node)) ||
-        (*rc = upload(&P->d_tiles, P->tiles))) {
-        free_plan_device(*P);
-        return nullptr;
+    // device copies of the task arrays, made on the plan's first launch
+    // through the library's own buffers (mp_gemm_noalloc copies them into its
+    // scratch array on every call instead)
+    if (device && !raw->on_device) {
+        if ((*rc = upload(&raw->d_gemm, raw->gemm)) || (*rc = upload(&raw->d_node, raw->node)) ||
+            (*rc = upload(&raw->d_tiles, raw->tiles))) {
+            free_plan_device(*raw);
+            return nullptr;
+        }
+        raw->on_device = true;
     }
-    Plan* raw = P.get();
-    S.plans[key] = std::move(P);
     return raw;
 }
 
@@ -276,6 +287,12 @@ int run_plan(const Plan& P, Bases bs, hipStream_t s)
 
 int launch_steps(const Plan& P, const Bases& bs, hipStream_t s)
 {
+    return launch_plan_steps(P, P.d_gemm, P.d_node, P.d_tiles, bs, s);
+}
+
+int launch_plan_steps(const Plan& P, const GemmTask* d_gemm, const NodeTask* d_node, const int32_t* d_tiles,
+                      const Bases& bs, hipStream_t s)
+{
     // the tile map holds indices into the plan's whole task arrays
     for (const Step& st : P.steps) {
         hipError_t e;
@@ -288,11 +305,9 @@ int launch_steps(const Plan& P, const Bases& bs, hipStream_t s)
             (void)hipEventRecord(pr.e0, s);
         }
         if (st.kind == 0)
-            e = launch_gemm(P.key.L, st.op, P.d_gemm, P.d_tiles + st.tile0, st.ntiles, bs,
-                            grid_for(st.ntiles), s);
+            e = launch_gemm(P.key.L, st.op, d_gemm, d_tiles + st.tile0, st.ntiles, bs, grid_for(st.ntiles), s);
         else
-            e = launch_node(P.key.L, st.op, P.d_node, P.d_tiles + st.tile0, st.ntiles, bs,
-                            grid_for(st.ntiles), s);
+            e = launch_node(P.key.L, st.op, d_node, d_tiles + st.tile0, st.ntiles, bs, grid_for(st.ntiles), s);
         if (prof) {
             (void)hipEventRecord(pr.e1, s);
             std::lock_guard<std::mutex> g(g_prof_mu);
@@ -314,7 +329,7 @@ int gemm_internal(int64_t m, int64_t l, int64_t n, int L, int algo, int cutoff, 
     PlanKey key{m, l, n, L, algo, cutoff, policy, algo == ALGO_BLOCK ? 1 : leaf, lda, psa, ldb, psb, ldc, psc};
     if (algo == ALGO_SIMPLE || algo == ALGO_BLOCK) key.cutoff = 0, key.policy = 0;
     int rc = MP_OK;
-    Plan* P = get_plan(key, &rc);
+    Plan* P = get_plan(key, &rc, true);
     if (!P) return rc ? rc : MP_E_NOMEM;
     Bases bs{};
     bs.p[BASE_A] = const_cast<uint32_t*>(A);
@@ -425,11 +440,16 @@ int mp_set_policy(int odd_policy, int leaf)
     return MP_OK;
 }
 
-int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, int policy, int leaf,
-               const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
-               uint32_t* C, int64_t ldc, int64_t psc)
+}  // extern "C"
+
+namespace mpg {
+
+int gemm_validate(int64_t m, int64_t l, int64_t n, int prec, int* algo_io, int* cutoff_io, int policy, int* leaf_io,
+                  const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
+                  const uint32_t* C, int64_t ldc, int64_t psc, int* L_out)
 {
     int L, rc;
+    int algo = *algo_io, cutoff = *cutoff_io, leaf = *leaf_io;
     if ((rc = check_prec(prec, &L))) return rc;
     if (algo < ALGO_SIMPLE || algo > ALGO_AUTO) return set_err(MP_E_ARG, "unknown algorithm");
     if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
@@ -446,9 +466,27 @@ int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, 
     if ((rc = check_mat("A", A, m, l, lda, psa)) || (rc = check_mat("B", B, l, n, ldb, psb)) ||
         (rc = check_mat("C", C, m, n, ldc, psc)))
         return rc;
-    if (m == 0 || n == 0) return MP_OK;
-    if (l > 0 && (overlaps(C, psc, A, psa, L) || overlaps(C, psc, B, psb, L)))
+    if (m > 0 && n > 0 && l > 0 && (overlaps(C, psc, A, psa, L) || overlaps(C, psc, B, psb, L)))
         return set_err(MP_E_ALIAS, "C overlaps A or B");
+    *algo_io = algo;
+    *cutoff_io = cutoff;
+    *leaf_io = leaf;
+    *L_out = L;
+    return MP_OK;
+}
+
+}  // namespace mpg
+
+extern "C" {
+
+int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, int policy, int leaf,
+               const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
+               uint32_t* C, int64_t ldc, int64_t psc)
+{
+    int L, rc;
+    if ((rc = gemm_validate(m, l, n, prec, &algo, &cutoff, policy, &leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, &L)))
+        return rc;
+    if (m == 0 || n == 0) return MP_OK;
     if ((rc = device_check())) return rc;
     rc = gemm_internal(m, l, n, L, algo, cutoff, policy, leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, g_stream);
     if (rc) return rc;

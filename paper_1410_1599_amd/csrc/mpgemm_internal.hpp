@@ -29,6 +29,27 @@ int gemm_internal(int64_t m, int64_t l, int64_t n, int L, int algo, int cutoff, 
                   const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
                   uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s);
 
+struct Plan;
+struct PlanKey;
+struct GemmTask;
+struct NodeTask;
+struct Bases;
+
+// The cached plan for key, built and validated on first use; with device
+// true its task arrays are also copied to device buffers of the library.
+Plan* get_plan(const PlanKey& key, int* rc, bool device);
+
+// Enqueue the plan's launches on s, reading its task arrays and tile map
+// from the given device copies.
+int launch_plan_steps(const Plan& P, const GemmTask* d_gemm, const NodeTask* d_node, const int32_t* d_tiles,
+                      const Bases& bs, hipStream_t s);
+
+// The argument checks of mp_gemm_ex; resolves MP_AUTO (algo, cutoff, leaf)
+// and returns the limb count in *L_out.
+int gemm_validate(int64_t m, int64_t l, int64_t n, int prec, int* algo_io, int* cutoff_io, int policy, int* leaf_io,
+                  const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
+                  const uint32_t* C, int64_t ldc, int64_t psc, int* L_out);
+
 // C := A op B elementwise through a cached one-task plan (no argument checks)
 int ew_internal(int op, int64_t m, int64_t n, int L, const uint32_t* A, int64_t lda, int64_t psa,
                 const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s);

@@ -61,7 +61,8 @@ struct Plan {
     int depth = 0;
     // operation counts of the plan (scalar MP multiplies and adds/subs)
     double n_mul = 0, n_addsub = 0;
-    // device copies
+    // device copies (made on the first launch through mp_gemm)
+    bool on_device = false;
     GemmTask* d_gemm = nullptr;
     NodeTask* d_node = nullptr;
     int32_t* d_tiles = nullptr;

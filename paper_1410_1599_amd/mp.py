@@ -49,6 +49,7 @@ def _load():
         "mp_set_policy": ([i32, i32], i32),
         "mp_gemm": ([i64, i64, i64, i32, i32, i32] + mat * 3, i32),
         "mp_gemm_ex": ([i64, i64, i64, i32, i32, i32, i32, i32] + mat * 3, i32),
+        "mp_gemm_noalloc": ([i64, i64, i64, i32, i32, i32] + mat * 3, i32),
         "mp_add": ([i64, i64, i32] + mat * 3, i32),
         "mp_sub": ([i64, i64, i32] + mat * 3, i32),
         "mp_mul_ew": ([i64, i64, i32] + mat * 3, i32),
@@ -142,6 +143,11 @@ def mp_set_policy(odd_policy=PEEL, leaf=LEAF_SIMPLE):
 def mp_gemm(m, l, n, prec, algo, cutoff, A, B, C):
     mp_set_stream()
     return _check(lib.mp_gemm(m, l, n, prec, int(algo), int(cutoff), *_mat(A), *_mat(B), *_mat(C)))
+
+
+def mp_gemm_noalloc(m, l, n, prec, algo, cutoff, A, B, C):
+    mp_set_stream()
+    return _check(lib.mp_gemm_noalloc(m, l, n, prec, int(algo), int(cutoff), *_mat(A), *_mat(B), *_mat(C)))
 
 
 def mp_gemm_ex(m, l, n, prec, algo, cutoff, policy, leaf, A, B, C):
