@@ -122,6 +122,13 @@ def parse(argv=None):
                     help="the paper's own matrices (Section 3: a_ij = sqrt5 (i+j-1), b_ij = sqrt3 (n-i+1)), cutoff 32, "
                          "mixed odd-size policy: square n = 255..2049 and Table 5's m = n = 1024 with l = 63..513 at "
                          "128 bits, square n = 255..2048 at 1024 bits and 255..512 at 8192 bits; 0: skip")
+    ap.add_argument("--launch-ab", type=int, default=0,
+                    help="time the headline product under every launch shape (leaf tile width 16/32/64 columns, "
+                         "a workgroup per tile or persistent grids) and the serving run with and without "
+                         "persistent grids; 0: skip")
+    ap.add_argument("--graph-ab", type=int, default=0,
+                    help="time graph replay against eager launches for Winograd products n = 64..512 at 256 bits "
+                         "(cutoff 32); 0: skip")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB device to device (a kernel of known traffic for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -473,6 +480,65 @@ def final_line(args, h, cpu=None, slice_res=None, accuracy=None, lu=None, c2=Non
     return out
 
 
+def launch_ab_section(args, mp, torch, h):
+    """ms per step of the headline product for every launch shape."""
+    n, p = args.n, args.prec
+    out = {"section": "launch_ab", "config": "mp_gemm m=l=n=%d prec=%d %s cutoff=%d; min over 3 runs of %d steps"
+                                             % (n, p, args.algo, args.cutoff, max(2, args.steps // 4))}
+    for tcl in (0, 5, 4):
+        for persist in (0, 1):
+            mp.mp_set_launch(tcl, persist)
+            try:
+                mp.mp_gemm(n, n, n, p, mp.ALGOS[args.algo], args.cutoff, h["dA"], h["dB"], h["dC"])
+                best = float("inf")
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(max(2, args.steps // 4)):
+                        mp.mp_gemm(n, n, n, p, mp.ALGOS[args.algo], args.cutoff, h["dA"], h["dB"], h["dC"])
+                    torch.cuda.synchronize()
+                    best = min(best, (time.perf_counter() - t0) / max(2, args.steps // 4))
+            finally:
+                mp.mp_set_launch(0, 0)
+            out["tile_cols_%d_%s" % (64 if tcl == 0 else 1 << tcl, "persistent" if persist else "per_tile")] = \
+                sig(best * 1e3)
+    return out
+
+
+def graph_ab_section(mp, torch, I):
+    """Eager launches against graph replay for small products (launch-bound)."""
+    p = 256
+    out = {"section": "graph_ab", "config": "mp_gemm n x n x n, 256 bits, Winograd cutoff 32, on a side stream; "
+                                            "ms per product, mean of 50 after one warm call"}
+    s = torch.cuda.Stream()
+    for n in (64, 128, 256, 512):
+        A = mp.to_device(I.uniform_pm1(n, n, p, 71))
+        B = mp.to_device(I.uniform_pm1(n, n, p, 72))
+        C = mp.empty(n, n, p)
+        info = mp.mp_plan_info(n, n, n, p, mp.WINOGRAD, 32)
+        row = {"launches": info["n_launches"]}
+        with torch.cuda.stream(s):
+            for mode in (0, 1):
+                mp.mp_set_graph_mode(mode)
+                try:
+                    s.synchronize()
+                    t0 = time.perf_counter()
+                    mp.mp_gemm(n, n, n, p, mp.WINOGRAD, 32, A, B, C)      # plan (and capture) on first use
+                    s.synchronize()
+                    first = time.perf_counter() - t0
+                    t0 = time.perf_counter()
+                    for _ in range(50):
+                        mp.mp_gemm(n, n, n, p, mp.WINOGRAD, 32, A, B, C)
+                    s.synchronize()
+                    row["graph" if mode else "eager"] = sig((time.perf_counter() - t0) / 50 * 1e3)
+                    if mode:
+                        row["capture_ms"] = sig(first * 1e3)
+                finally:
+                    mp.mp_set_graph_mode(0)
+        out[n] = row
+    return out
+
+
 def extended_sections(args, mp, torch, I):
     """Opt-in sections, each printed as its own JSON line."""
     if args.lu_paper:
@@ -642,6 +708,11 @@ def main(argv=None):
     h = headline(args, mp, torch, I, A, B)
     print("# headline %.3f ms/step, parity: %s" % (h["ms"], h["parity"]), file=sys.stderr, flush=True)
 
+    if args.launch_ab:
+        print(json.dumps(launch_ab_section(args, mp, torch, h)), flush=True)
+    if args.graph_ab:
+        print(json.dumps(graph_ab_section(mp, torch, I)), flush=True)
+
     slice_res, slice_host = None, None
     if args.slice_steps > 0:
         slice_res, slice_host = slice_section(args, mp, torch, h)
@@ -651,6 +722,13 @@ def main(argv=None):
     lu = lu_section(mp, torch, I) if args.lu else None
     c2 = c2_section(mp, torch, I) if args.c2 else None
     serve_res = serve_section(args, mp, torch) if args.serve_requests > 0 else None
+    if args.launch_ab and args.serve_requests > 0:
+        mp.mp_set_launch(0, 1)
+        try:
+            alt = serve_section(args, mp, torch)
+        finally:
+            mp.mp_set_launch(0, 0)
+        print(json.dumps({"section": "serve_launch_ab", "per_tile": serve_res, "persistent": alt}), flush=True)
     extended_sections(args, mp, torch, I)
     cpu = None if args.no_cpu else cpu_baseline(args, A, B)
 

@@ -316,19 +316,34 @@ int mp_fill_uniform(int64_t rows, int64_t cols, int prec, uint32_t *X, int64_t l
 int mp_set_graph_mode(int enable);
 
 /*
+ * Launch shape of the products (process-wide; the paper leaves tuning to
+ * future work, Section 5).  tile_cols_log2: a leaf tile of the Simple kernel
+ * covers 2^t columns x 256 / 2^t rows (t = 4, 5 or 6; 0 is the default, 64
+ * columns; Block always uses 64).  persistent = 1: every grouped launch runs
+ * a grid of as many workgroups as the device keeps resident, which stride over
+ * the tiles; 0: one workgroup per tile.  Neither changes any result bit (each
+ * element's operation order is fixed).  MP_E_ARG for other values.
+ */
+int mp_set_launch(int tile_cols_log2, int persistent);
+
+/*
  * Autotuner.  mp_tune times Simple, Block, and Strassen / Winograd with cutoffs
  * 32, 64, 128, 256 (below min(m, l, n)) and both leaf kernels on library-owned
  * scratch operands of the given shape (uniform (-1, 1) values), `reps` runs
- * each on the calling thread's stream, and records the fastest for
- * (prec, ceil(log2 m), ceil(log2 l), ceil(log2 n)).  Outputs (host, may be
- * NULL): the choice and its milliseconds.  Synchronises the stream.
- * mp_auto_choice reports what MP_AUTO would use.  mp_tune_save writes the
+ * each on the calling thread's stream, then the fastest with leaf tiles of 16,
+ * 32 and 64 columns, each with and without persistent grids, and records the
+ * fastest for (prec, ceil(log2 m), ceil(log2 l), ceil(log2 n)).  Outputs
+ * (host, may be NULL): the choice and its milliseconds.  Synchronises the
+ * stream.  mp_auto_choice reports what MP_AUTO would use, mp_auto_launch also
+ * its launch shape (as mp_set_launch takes it).  mp_tune_save writes the
  * table as JSON; mp_tune_load reads such a file and returns the entries read
- * (negative on error).  Different choices give different (each correctly
- * rounded per operation) results.
+ * (negative on error).  Different algorithm choices give different (each
+ * correctly rounded per operation) results; the launch shape gives none.
  */
 int mp_tune(int64_t m, int64_t l, int64_t n, int prec, int reps, int *algo, int *cutoff, int *leaf, float *ms);
 int mp_auto_choice(int64_t m, int64_t l, int64_t n, int prec, int *algo, int *cutoff, int *leaf);
+int mp_auto_launch(int64_t m, int64_t l, int64_t n, int prec, int *algo, int *cutoff, int *leaf,
+                   int *tile_cols_log2, int *persistent);
 int mp_tune_save(const char *path);
 int mp_tune_load(const char *path);
 

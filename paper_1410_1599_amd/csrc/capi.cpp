@@ -50,6 +50,7 @@ struct GraphKey {
 struct TuneEntry {
     int algo, cutoff, leaf;
     float ms;
+    int tcl = 0, persist = 0;       // leaf tile width (log2 columns, 0: 64) and persistent grids
 };
 
 struct DeviceState {
@@ -304,10 +305,12 @@ int launch_plan_steps(const Plan& P, const GemmTask* d_gemm, const NodeTask* d_n
             (void)hipEventCreate(&pr.e1);
             (void)hipEventRecord(pr.e0, s);
         }
+        // persistent plans launch grids of resident workgroups (grid 0: sized by the launcher)
+        const int64_t grid = P.key.persist ? 0 : grid_for(st.ntiles);
         if (st.kind == 0)
-            e = launch_gemm(P.key.L, st.op, d_gemm, d_tiles + st.tile0, st.ntiles, bs, grid_for(st.ntiles), s);
+            e = launch_gemm(P.key.L, st.op, d_gemm, d_tiles + st.tile0, st.ntiles, bs, grid, s);
         else
-            e = launch_node(P.key.L, st.op, d_node, d_tiles + st.tile0, st.ntiles, bs, grid_for(st.ntiles), s);
+            e = launch_node(P.key.L, st.op, d_node, d_tiles + st.tile0, st.ntiles, bs, grid, s);
         if (prof) {
             (void)hipEventRecord(pr.e1, s);
             std::lock_guard<std::mutex> g(g_prof_mu);
@@ -323,10 +326,13 @@ int launch_plan_steps(const Plan& P, const GemmTask* d_gemm, const NodeTask* d_n
 
 int gemm_internal(int64_t m, int64_t l, int64_t n, int L, int algo, int cutoff, int policy, int leaf,
                   const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
-                  uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s)
+                  uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s, int tcl, int persist)
 {
     if (m == 0 || n == 0) return MP_OK;
     PlanKey key{m, l, n, L, algo, cutoff, policy, algo == ALGO_BLOCK ? 1 : leaf, lda, psa, ldb, psb, ldc, psc};
+    key.tcl = tcl >= 0 ? tcl : g_tcl;
+    key.persist = persist >= 0 ? persist : g_persist;
+    if (algo == ALGO_BLOCK) key.tcl = 0;
     if (algo == ALGO_SIMPLE || algo == ALGO_BLOCK) key.cutoff = 0, key.policy = 0;
     int rc = MP_OK;
     Plan* P = get_plan(key, &rc, true);
@@ -399,15 +405,19 @@ bool tune_lookup(int64_t m, int64_t l, int64_t n, int prec, TuneEntry* out)
     return true;
 }
 
+extern int g_tcl, g_persist;
+
 // default when nothing was tuned: Winograd down to 64 (Simple below)
 TuneEntry tune_default(int64_t m, int64_t l, int64_t n)
 {
-    if (std::min(m, std::min(l, n)) > 64) return TuneEntry{ALGO_WINOGRAD, 64, LEAF_SIMPLE, 0.f};
-    return TuneEntry{ALGO_SIMPLE, 0, LEAF_SIMPLE, 0.f};
+    if (std::min(m, std::min(l, n)) > 64) return TuneEntry{ALGO_WINOGRAD, 64, LEAF_SIMPLE, 0.f, g_tcl, g_persist};
+    return TuneEntry{ALGO_SIMPLE, 0, LEAF_SIMPLE, 0.f, g_tcl, g_persist};
 }
 
 int g_leaf = LEAF_SIMPLE;
 int g_policy = POLICY_PEEL;
+int g_tcl = 0;
+int g_persist = 0;
 
 }  // namespace mpg
 
@@ -446,10 +456,11 @@ namespace mpg {
 
 int gemm_validate(int64_t m, int64_t l, int64_t n, int prec, int* algo_io, int* cutoff_io, int policy, int* leaf_io,
                   const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
-                  const uint32_t* C, int64_t ldc, int64_t psc, int* L_out)
+                  const uint32_t* C, int64_t ldc, int64_t psc, int* L_out, int* tcl_out, int* persist_out)
 {
     int L, rc;
     int algo = *algo_io, cutoff = *cutoff_io, leaf = *leaf_io;
+    int tcl = g_tcl, persist = g_persist;
     if ((rc = check_prec(prec, &L))) return rc;
     if (algo < ALGO_SIMPLE || algo > ALGO_AUTO) return set_err(MP_E_ARG, "unknown algorithm");
     if ((algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) && cutoff < 1) return set_err(MP_E_ARG, "cutoff must be >= 1");
@@ -462,6 +473,8 @@ int gemm_validate(int64_t m, int64_t l, int64_t n, int prec, int* algo_io, int* 
         algo = t.algo;
         cutoff = t.cutoff;
         leaf = t.leaf;
+        tcl = t.tcl;
+        persist = t.persist;
     }
     if ((rc = check_mat("A", A, m, l, lda, psa)) || (rc = check_mat("B", B, l, n, ldb, psb)) ||
         (rc = check_mat("C", C, m, n, ldc, psc)))
@@ -472,6 +485,8 @@ int gemm_validate(int64_t m, int64_t l, int64_t n, int prec, int* algo_io, int* 
     *cutoff_io = cutoff;
     *leaf_io = leaf;
     *L_out = L;
+    if (tcl_out) *tcl_out = tcl;
+    if (persist_out) *persist_out = persist;
     return MP_OK;
 }
 
@@ -483,12 +498,14 @@ int mp_gemm_ex(int64_t m, int64_t l, int64_t n, int prec, int algo, int cutoff, 
                const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
                uint32_t* C, int64_t ldc, int64_t psc)
 {
-    int L, rc;
-    if ((rc = gemm_validate(m, l, n, prec, &algo, &cutoff, policy, &leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, &L)))
+    int L, rc, tcl, persist;
+    if ((rc = gemm_validate(m, l, n, prec, &algo, &cutoff, policy, &leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, &L,
+                            &tcl, &persist)))
         return rc;
     if (m == 0 || n == 0) return MP_OK;
     if ((rc = device_check())) return rc;
-    rc = gemm_internal(m, l, n, L, algo, cutoff, policy, leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, g_stream);
+    rc = gemm_internal(m, l, n, L, algo, cutoff, policy, leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, g_stream, tcl,
+                       persist);
     if (rc) return rc;
     return device_check();
 }
@@ -640,6 +657,8 @@ int mp_gemm_batched(int count, const int64_t* m, const int64_t* l, const int64_t
     Plan P;
     PlanKey key{0, 0, 0, L, algo, (algo == ALGO_STRASSEN || algo == ALGO_WINOGRAD) ? cutoff : 0, g_policy,
                 algo == ALGO_BLOCK ? 1 : g_leaf, 0, 0, 0, 0, 0, 0};
+    key.tcl = algo == ALGO_BLOCK ? 0 : g_tcl;
+    key.persist = g_persist;
     build_plan_batched(P, key, items);
     const char* why = nullptr;
     if (!validate_plan(P, &why)) return set_err(MP_E_ARG, why);
@@ -691,6 +710,12 @@ int mp_set_graph_mode(int enable)
 
 int mp_auto_choice(int64_t m, int64_t l, int64_t n, int prec, int* algo, int* cutoff, int* leaf)
 {
+    return mp_auto_launch(m, l, n, prec, algo, cutoff, leaf, nullptr, nullptr);
+}
+
+int mp_auto_launch(int64_t m, int64_t l, int64_t n, int prec, int* algo, int* cutoff, int* leaf, int* tile_cols_log2,
+                   int* persistent)
+{
     int L, rc;
     if ((rc = check_prec(prec, &L))) return rc;
     TuneEntry t;
@@ -698,6 +723,18 @@ int mp_auto_choice(int64_t m, int64_t l, int64_t n, int prec, int* algo, int* cu
     if (algo) *algo = t.algo;
     if (cutoff) *cutoff = t.cutoff;
     if (leaf) *leaf = t.leaf;
+    if (tile_cols_log2) *tile_cols_log2 = t.tcl;
+    if (persistent) *persistent = t.persist;
+    return MP_OK;
+}
+
+int mp_set_launch(int tile_cols_log2, int persistent)
+{
+    if (tile_cols_log2 != 0 && (tile_cols_log2 < 4 || tile_cols_log2 > 6))
+        return set_err(MP_E_ARG, "tile_cols_log2 must be 0 (64 columns) or 4 .. 6");
+    if (persistent != 0 && persistent != 1) return set_err(MP_E_ARG, "persistent must be 0 or 1");
+    g_tcl = tile_cols_log2 == 6 ? 0 : tile_cols_log2;
+    g_persist = persistent;
     return MP_OK;
 }
 
@@ -722,6 +759,9 @@ int mp_tune(int64_t m, int64_t l, int64_t n, int prec, int reps, int* algo, int*
         (void)hipFree(buf);
         return set_err(MP_E_DEVICE, "tuner fill failed");
     }
+    // stage 1: algorithm, cutoff and leaf kernel with the default launch
+    // (64-column tiles, a workgroup per tile); stage 2: the tile width and
+    // the persistent grid for the winner
     std::vector<TuneEntry> cand = {{ALGO_SIMPLE, 0, LEAF_SIMPLE, 0.f}, {ALGO_BLOCK, 0, LEAF_BLOCK, 0.f}};
     const int64_t mn = std::min(m, std::min(l, n));
     for (int a : {ALGO_WINOGRAD, ALGO_STRASSEN})
@@ -731,20 +771,41 @@ int mp_tune(int64_t m, int64_t l, int64_t n, int prec, int reps, int* algo, int*
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    TuneEntry best{ALGO_SIMPLE, 0, LEAF_SIMPLE, 1e30f};
-    for (TuneEntry& t : cand) {
-        rc = gemm_internal(m, l, n, L, t.algo, t.cutoff, POLICY_PEEL, t.leaf, A, l, m * l, B, n, l * n, C, n, m * n, s);
-        if (rc) break;
+    auto time_one = [&](TuneEntry& t) {
+        rc = gemm_internal(m, l, n, L, t.algo, t.cutoff, POLICY_PEEL, t.leaf, A, l, m * l, B, n, l * n, C, n, m * n, s,
+                           t.tcl, t.persist);
+        if (rc) return;
         (void)hipEventRecord(e0, s);
         for (int r = 0; r < reps && !rc; r++)
             rc = gemm_internal(m, l, n, L, t.algo, t.cutoff, POLICY_PEEL, t.leaf, A, l, m * l, B, n, l * n, C, n,
-                               m * n, s);
+                               m * n, s, t.tcl, t.persist);
         (void)hipEventRecord(e1, s);
         (void)hipEventSynchronize(e1);
         float t_ms = 0;
         (void)hipEventElapsedTime(&t_ms, e0, e1);
         t.ms = t_ms / reps;
+    };
+    TuneEntry best{ALGO_SIMPLE, 0, LEAF_SIMPLE, 1e30f};
+    for (TuneEntry& t : cand) {
+        time_one(t);
+        if (rc) break;
         if (t.ms < best.ms) best = t;
+    }
+    if (!rc) {
+        std::vector<TuneEntry> launch;
+        for (int tc : {0, 5, 4})
+            for (int pe : {0, 1}) {
+                if ((tc == 0 && pe == 0) || (tc != 0 && best.leaf == LEAF_BLOCK)) continue;
+                TuneEntry t = best;
+                t.tcl = tc;
+                t.persist = pe;
+                launch.push_back(t);
+            }
+        for (TuneEntry& t : launch) {
+            time_one(t);
+            if (rc) break;
+            if (t.ms < best.ms) best = t;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -772,9 +833,10 @@ int mp_tune_save(const char* path)
     bool first = true;
     for (auto& kv : g_tune) {
         fprintf(f, "%s\n {\"prec\": %lld, \"m_log2\": %lld, \"l_log2\": %lld, \"n_log2\": %lld, \"algo\": %d, "
-                   "\"cutoff\": %d, \"leaf\": %d, \"ms\": %.4f}",
+                   "\"cutoff\": %d, \"leaf\": %d, \"ms\": %.4f, \"tile_cols_log2\": %d, \"persistent\": %d}",
                 first ? "" : ",", (long long)kv.first[0], (long long)kv.first[1], (long long)kv.first[2],
-                (long long)kv.first[3], kv.second.algo, kv.second.cutoff, kv.second.leaf, kv.second.ms);
+                (long long)kv.first[3], kv.second.algo, kv.second.cutoff, kv.second.leaf, kv.second.ms,
+                kv.second.tcl, kv.second.persist);
         first = false;
     }
     fprintf(f, "\n]\n");
@@ -788,7 +850,7 @@ int mp_tune_load(const char* path)
     FILE* f = fopen(path, "r");
     if (!f) return set_err(MP_E_ARG, "cannot open the tuning file");
     long long pr, a, b, c;
-    int al, cu, lf;
+    int al, cu, lf, tc = 0, pe = 0;
     float t;
     int got = 0;
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -797,8 +859,12 @@ int mp_tune_load(const char* path)
         if (sscanf(line, " {\"prec\": %lld, \"m_log2\": %lld, \"l_log2\": %lld, \"n_log2\": %lld, \"algo\": %d, "
                          "\"cutoff\": %d, \"leaf\": %d, \"ms\": %f}",
                    &pr, &a, &b, &c, &al, &cu, &lf, &t) == 8) {
+            // the launch fields are optional (files written before they existed)
+            const char* q = strstr(line, "\"tile_cols_log2\":");
+            if (!q || sscanf(q, "\"tile_cols_log2\": %d, \"persistent\": %d", &tc, &pe) != 2) tc = 0, pe = 0;
             if (al < ALGO_SIMPLE || al > ALGO_WINOGRAD || lf < 0 || lf > 1 || cu < 0) continue;
-            g_tune[{pr, a, b, c}] = TuneEntry{al, cu, lf, t};
+            if ((tc != 0 && (tc < 4 || tc > 6)) || (pe != 0 && pe != 1)) continue;
+            g_tune[{pr, a, b, c}] = TuneEntry{al, cu, lf, t, tc == 6 ? 0 : tc, pe};
             got++;
         }
     }

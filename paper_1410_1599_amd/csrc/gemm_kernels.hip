@@ -13,6 +13,10 @@
 // Strassen/Winograd plan plus its peel products) is cut into tiles, and
 // tile_task maps a tile to its task.  The grid may be smaller than the tile
 // count (persistent mode): workgroups stride over the tiles.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "launch.hpp"
 #include "mp_arith.hpp"
 #include "node_ops.hpp"
@@ -282,6 +286,46 @@ k_transpose(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile
 
 // ------------------------------------------------------------------ launchers
 
+// Grid of a launch: `grid` workgroups, or with grid <= 0 a persistent grid of
+// as many workgroups as the device keeps resident at once (compute units x
+// the kernel's occupancy per unit, from its register and LDS use), capped by
+// the tile count; the kernels stride over the tiles either way.
+static int device_cus()
+{
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+    return n;
+}
+
+template <class K>
+static int64_t launch_grid(K kernel, int block, int64_t ntiles, int64_t grid)
+{
+    if (grid > 0) return grid;
+    static std::mutex mu;
+    static std::map<const void*, int> occ;            // kernel -> resident workgroups per compute unit
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = occ.find((const void*)kernel);
+        if (it != occ.end()) {
+            per_cu = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            occ[(const void*)kernel] = per_cu;
+        }
+    }
+    return std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)device_cus() * per_cu));
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t* X, int64_t count, int32_t value)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -315,18 +359,22 @@ static hipError_t gemm_launch_L(int kind, const GemmTask* tasks, const int32_t* 
                                 const Bases& bs, int64_t grid, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    const dim3 g((unsigned)grid);
-    if (kind == LEAF_BLOCK)
-        hipLaunchKernelGGL((k_gemm_block<L, GEMM_TM, BLOCK_TK>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles, bs);
-    else
+    if (kind == LEAF_BLOCK) {
+        const dim3 g((unsigned)launch_grid(k_gemm_block<L, GEMM_TM, BLOCK_TK>, 64 * GEMM_TM, ntiles, grid));
+        hipLaunchKernelGGL((k_gemm_block<L, GEMM_TM, BLOCK_TK>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles,
+                           bs);
+    } else {
+        const dim3 g((unsigned)launch_grid(k_gemm_simple<L, GEMM_TM>, 64 * GEMM_TM, ntiles, grid));
         hipLaunchKernelGGL((k_gemm_simple<L, GEMM_TM>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles, bs);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_gemm(int L, int kind, const GemmTask* tasks, const int32_t* tile_task, int64_t ntiles,
                        const Bases& bs, int64_t grid, hipStream_t s)
 {
-    if (L >= 64) return launch_gemm_wide(L, tasks, tile_task, ntiles, bs, grid, s);   // Block = Simple's order
+    if (L >= 64)                        // Block = Simple's order; a wave per element, grids per tile
+        return launch_gemm_wide(L, tasks, tile_task, ntiles, bs, grid > 0 ? grid : ntiles, s);
     switch (L) {
     case 4: return gemm_launch_L<4>(kind, tasks, tile_task, ntiles, bs, grid, s);
     case 8: return gemm_launch_L<8>(kind, tasks, tile_task, ntiles, bs, grid, s);
@@ -340,7 +388,8 @@ template <int L, int OP>
 static void node_launch_one(const NodeTask* tasks, const int32_t* tile_task, int64_t ntiles, const Bases& bs,
                             int64_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_node<L, OP>), dim3((unsigned)grid), dim3(NODE_TILE), 0, s, tasks, tile_task, ntiles, bs);
+    const dim3 g((unsigned)launch_grid(k_node<L, OP>, NODE_TILE, ntiles, grid));
+    hipLaunchKernelGGL((k_node<L, OP>), g, dim3(NODE_TILE), 0, s, tasks, tile_task, ntiles, bs);
 }
 
 template <int L>
@@ -371,10 +420,11 @@ hipError_t launch_node(int L, int op, const NodeTask* tasks, const int32_t* tile
 {
     if (op == OP_TRANSPOSE) {           // word copies: one kernel for every precision
         if (ntiles <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k_transpose, dim3((unsigned)grid), dim3(256), 0, s, tasks, tile_task, ntiles, bs, L + 2);
+        hipLaunchKernelGGL(k_transpose, dim3((unsigned)launch_grid(k_transpose, 256, ntiles, grid)), dim3(256), 0, s,
+                           tasks, tile_task, ntiles, bs, L + 2);
         return hipGetLastError();
     }
-    if (L >= 64) return launch_node_wide(L, op, tasks, tile_task, ntiles, bs, grid, s);
+    if (L >= 64) return launch_node_wide(L, op, tasks, tile_task, ntiles, bs, grid > 0 ? grid : ntiles, s);
     switch (L) {
     case 4: return node_launch_L<4>(op, tasks, tile_task, ntiles, bs, grid, s);
     case 8: return node_launch_L<8>(op, tasks, tile_task, ntiles, bs, grid, s);

@@ -14,6 +14,8 @@ extern thread_local hipStream_t g_stream;
 extern thread_local std::string g_err;
 extern int g_leaf;
 extern int g_policy;
+extern int g_tcl;         // leaf tile width, log2 columns (0: 64 columns)
+extern int g_persist;     // persistent grids
 
 int set_err(int code, const char* msg);
 int check_prec(int prec, int* L);
@@ -24,10 +26,11 @@ enum WsSlot { WS_PLAN = 0, WS_LU = 1, WS_SLICE = 2, WS_SLICE_EXP = 3, WS_BATCH =
 // per-stream, per-slot device buffer of at least `words` uint32 (grown on demand)
 uint32_t* workspace(size_t words, hipStream_t s, int slot, int* rc);
 
-// C := A B through a cached plan (no argument checks)
+// C := A B through a cached plan (no argument checks); tcl / persist < 0
+// take the process settings of mp_set_launch
 int gemm_internal(int64_t m, int64_t l, int64_t n, int L, int algo, int cutoff, int policy, int leaf,
                   const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
-                  uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s);
+                  uint32_t* C, int64_t ldc, int64_t psc, hipStream_t s, int tcl = -1, int persist = -1);
 
 struct Plan;
 struct PlanKey;
@@ -48,7 +51,8 @@ int launch_plan_steps(const Plan& P, const GemmTask* d_gemm, const NodeTask* d_n
 // and returns the limb count in *L_out.
 int gemm_validate(int64_t m, int64_t l, int64_t n, int prec, int* algo_io, int* cutoff_io, int policy, int* leaf_io,
                   const uint32_t* A, int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb,
-                  const uint32_t* C, int64_t ldc, int64_t psc, int* L_out);
+                  const uint32_t* C, int64_t ldc, int64_t psc, int* L_out, int* tcl_out = nullptr,
+                  int* persist_out = nullptr);
 
 // C := A op B elementwise through a cached one-task plan (no argument checks)
 int ew_internal(int op, int64_t m, int64_t n, int L, const uint32_t* A, int64_t lda, int64_t psa,

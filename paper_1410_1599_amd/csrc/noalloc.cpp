@@ -70,12 +70,15 @@ extern "C" int mp_gemm_noalloc(int64_t m, int64_t l, int64_t n, int prec, int al
                                int64_t lda, int64_t psa, const uint32_t* B, int64_t ldb, int64_t psb, uint32_t* C,
                                int64_t ldc, int64_t psc)
 {
-    int L, rc;
+    int L, rc, tcl, persist;
     int leaf = g_leaf, policy = g_policy;
-    if ((rc = gemm_validate(m, l, n, prec, &algo, &cutoff, policy, &leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, &L)))
+    if ((rc = gemm_validate(m, l, n, prec, &algo, &cutoff, policy, &leaf, A, lda, psa, B, ldb, psb, C, ldc, psc, &L,
+                            &tcl, &persist)))
         return rc;
     if (m == 0 || n == 0) return MP_OK;
     PlanKey key{m, l, n, L, algo, cutoff, policy, algo == ALGO_BLOCK ? 1 : leaf, lda, psa, ldb, psb, ldc, psc};
+    key.tcl = algo == ALGO_BLOCK ? 0 : tcl;
+    key.persist = persist;
     if (algo == ALGO_SIMPLE || algo == ALGO_BLOCK) key.cutoff = 0, key.policy = 0;
     // the plan is host memory only (built and validated once, cached)
     Plan* P = get_plan(key, &rc, false);

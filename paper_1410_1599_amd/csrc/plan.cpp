@@ -10,7 +10,7 @@ bool PlanKey::operator==(const PlanKey& o) const
 {
     return m == o.m && l == o.l && n == o.n && L == o.L && algo == o.algo && cutoff == o.cutoff &&
            policy == o.policy && leaf == o.leaf && lda == o.lda && psa == o.psa && ldb == o.ldb &&
-           psb == o.psb && ldc == o.ldc && psc == o.psc;
+           psb == o.psb && ldc == o.ldc && psc == o.psc && tcl == o.tcl && persist == o.persist;
 }
 
 size_t PlanKeyHash::operator()(const PlanKey& k) const
@@ -18,7 +18,7 @@ size_t PlanKeyHash::operator()(const PlanKey& k) const
     size_t h = 1469598103934665603ull;
     auto mix = [&](int64_t v) { h = (h ^ (size_t)v) * 1099511628211ull; };
     mix(k.m); mix(k.l); mix(k.n); mix(k.L); mix(k.algo); mix(k.cutoff); mix(k.policy); mix(k.leaf);
-    mix(k.lda); mix(k.psa); mix(k.ldb); mix(k.psb); mix(k.ldc); mix(k.psc);
+    mix(k.lda); mix(k.psa); mix(k.ldb); mix(k.psb); mix(k.ldc); mix(k.psc); mix(k.tcl); mix(k.persist);
     return h;
 }
 
@@ -94,7 +94,7 @@ struct Builder {
         GemmTask t{};
         t.A = A; t.B = B; t.C = C;
         t.m = (int32_t)m; t.l = (int32_t)l; t.n = (int32_t)n; t.accum = accum; t.at = at;
-        t.tcl = (k.leaf == 1) ? 6 : std::min(6, ceil_log2(n));
+        t.tcl = (k.leaf == 1) ? 6 : std::min(k.tcl > 0 ? k.tcl : 6, ceil_log2(n));
         v.push_back(t);
         n_mul += (double)m * l * n;
         n_addsub += (double)m * l * n;

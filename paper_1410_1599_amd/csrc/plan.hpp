@@ -43,6 +43,8 @@ struct PlanKey {
     int64_t m, l, n;
     int L, algo, cutoff, policy, leaf;
     int64_t lda, psa, ldb, psb, ldc, psc;
+    int tcl = 0;          // leaf tile width 2^tcl columns (4..6; 0: 64 columns), Simple leaves only
+    int persist = 0;      // 1: grids of resident workgroups that stride over the tiles
     bool operator==(const PlanKey& o) const;
 };
 

@@ -69,6 +69,8 @@ def _load():
         "mp_gemm_batched": ([i32, i64p, i64p, i64p, i32, i32, i32] + [ctypes.POINTER(vp), i64p, i64p] * 3, i32),
         "mp_tune": ([i64, i64, i64, i32, i32, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float)], i32),
         "mp_auto_choice": ([i64, i64, i64, i32, i32p, i32p, i32p], i32),
+        "mp_auto_launch": ([i64, i64, i64, i32, i32p, i32p, i32p, i32p, i32p], i32),
+        "mp_set_launch": ([i32, i32], i32),
         "mp_tune_save": ([ctypes.c_char_p], i32),
         "mp_tune_load": ([ctypes.c_char_p], i32),
         "mp_lu_async": ([i64, i32, vp, i64, i64, vp, vp, i32, i32, i32, i32], i32),
@@ -272,6 +274,16 @@ def mp_auto_choice(m, l, n, prec):
     a, c, lf = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
     _check(lib.mp_auto_choice(m, l, n, prec, ctypes.byref(a), ctypes.byref(c), ctypes.byref(lf)))
     return {"algo": a.value, "cutoff": c.value, "leaf": lf.value}
+
+
+def mp_auto_launch(m, l, n, prec):
+    v = [ctypes.c_int(0) for _ in range(5)]
+    _check(lib.mp_auto_launch(m, l, n, prec, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("algo", "cutoff", "leaf", "tile_cols_log2", "persistent"), (x.value for x in v)))
+
+
+def mp_set_launch(tile_cols_log2=0, persistent=0):
+    return _check(lib.mp_set_launch(int(tile_cols_log2), int(persistent)))
 
 
 def mp_tune_save(path):

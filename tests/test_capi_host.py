@@ -156,3 +156,12 @@ def test_slice_inner_size_limit_without_device(mp):
                            ctypes.c_void_p(C), 4, 16, w)
     assert rc == -6, rc
     assert "131008" in mp.last_error()
+
+
+def test_launch_settings_without_device(mp):
+    lib = mp.lib
+    assert lib.mp_set_launch(3, 0) == -1
+    assert lib.mp_set_launch(7, 0) == -1
+    assert lib.mp_set_launch(0, 2) == -1
+    assert lib.mp_set_launch(5, 1) == 0
+    assert lib.mp_set_launch(0, 0) == 0

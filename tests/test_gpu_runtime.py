@@ -44,12 +44,48 @@ def test_graph_replays_match_eager_and_oracle():
         mp.mp_set_graph_mode(False)
 
 
+@pytest.mark.parametrize("tcl,persist", [(0, 1), (5, 0), (5, 1), (4, 0), (4, 1)])
+def test_launch_shapes_give_the_same_bits(tcl, persist):
+    """Leaf tile width and persistent grids change no result bit: a ragged
+    Winograd product (peels at every level, border tasks, many tiles) and a
+    Block product against the default launch and the oracle."""
+    p = 256
+    m, l, n = 203, 150, 177
+    A = I.uniform_pm1(m, l, p, 61)
+    B = I.log_uniform(l, n, p, 62, -12, 12)
+    dA, dB = mp.to_device(A), mp.to_device(B)
+    ref, got = mp.empty(m, n, p), mp.empty(m, n, p)
+    refb, gotb = mp.empty(m, n, p), mp.empty(m, n, p)
+    mp.mp_gemm(m, l, n, p, mp.WINOGRAD, 16, dA, dB, ref)
+    mp.mp_gemm(m, l, n, p, mp.BLOCK, 0, dA, dB, refb)
+    mp.mp_set_launch(tcl, persist)
+    try:
+        mp.mp_gemm(m, l, n, p, mp.WINOGRAD, 16, dA, dB, got)
+        mp.mp_gemm(m, l, n, p, mp.BLOCK, 0, dA, dB, gotb)
+    finally:
+        mp.mp_set_launch(0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, got) and torch.equal(refb, gotb)
+    want = cref.gemm(A, B, p, algo="winograd", cutoff=16)
+    assert planes_equal(mp.to_host(got), want)
+
+
+def test_launch_settings_rejected():
+    with pytest.raises(mp.MPError):
+        mp.mp_set_launch(3, 0)
+    with pytest.raises(mp.MPError):
+        mp.mp_set_launch(0, 2)
+
+
 def test_tuner_and_auto_choice_reproducible():
     p = 256
     m, l, n = 130, 96, 140
     choice = mp.mp_tune(m, l, n, p, reps=1)
     assert choice["algo"] in (0, 1, 2, 3) and choice["ms"] > 0
     assert mp.mp_auto_choice(m, l, n, p) == {k: choice[k] for k in ("algo", "cutoff", "leaf")}
+    launch = mp.mp_auto_launch(m, l, n, p)
+    assert {k: launch[k] for k in ("algo", "cutoff", "leaf")} == mp.mp_auto_choice(m, l, n, p)
+    assert launch["tile_cols_log2"] in (0, 4, 5) and launch["persistent"] in (0, 1)
     A = I.uniform_pm1(m, l, p, 7)
     B = I.uniform_pm1(l, n, p, 8)
     dA, dB = mp.to_device(A), mp.to_device(B)
@@ -66,6 +102,7 @@ def test_tuner_and_auto_choice_reproducible():
         path = os.path.join(d, "tune.json")
         mp.mp_tune_save(path)
         assert mp.mp_tune_load(path) >= 1
+        assert mp.mp_auto_launch(m, l, n, p) == launch
 
 
 def test_lu_async_matches_lu_ex():
