@@ -60,3 +60,25 @@ def test_fill_uniform_values_in_range():
     assert ((h[L - 1] >> 31) == 1).mean() > 0.99          # normalised mantissas
     e = h[L].view(np.int32)
     assert (e <= 0).all() and (e > -64).all()              # |x| < 1
+
+
+def test_binding_budget_refuses_queues_and_matches_alone():
+    """A 0.3 GB budget binds on this mix: the requests whose footprint alone
+    exceeds it are refused (never launched), others wait for memory to free
+    up, admitted memory never exceeds the budget, and results are the same
+    bits as the same requests run alone."""
+    reqs = serve.make_requests(120, 3000.0, seed=22)
+    budget = 0.3 * 2 ** 30
+    keep = {r.rid for r in reqs[::3]}
+    srv = serve.Server(slots=4, hbm_budget_gb=0.3, keep=keep)
+    st = srv.run(reqs)
+    want_refused = {r.rid for r in reqs if serve.footprint(r) > budget}
+    assert len(want_refused) >= 2
+    assert {r.rid for r in reqs if r.status == serve.REFUSED} == want_refused
+    assert all(r.status == serve.OK for r in reqs if r.rid not in want_refused)
+    assert st["waited_for_memory"] > 0
+    assert st["peak_admitted_gb"] <= 0.3
+    sample = [r for r in reqs if r.rid in keep and r.status == serve.OK]
+    ref = srv.alone(sample)
+    for r in sample:
+        assert planes_equal(ref[r.rid], r.result), r.rid
