@@ -9,4 +9,5 @@ imports nothing from the library.  Modules:
 * lu     -- blocked LU with partial pivoting, solve, exact residual
 * exact  -- exact products and ulp errors (yardstick for the slice path)
 * cref   -- ctypes wrapper of the C twin in oracle/c/mpref.c (large sizes)
+* conditioning -- exact condition numbers of the Lotkin matrix (Section 4)
 """
