@@ -20,6 +20,11 @@ LIB_WIDE = os.path.join(HERE, "libmpref_wide.so")
 MAXL_WIDE = 656
 
 
+# the host sanitizer builds (tests/test_host_sanitizers.py): address and
+# undefined-behaviour checks, every finding fatal
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
 def _build_one(lib, defines, force):
     if not force and os.path.exists(lib) and os.path.getmtime(lib) >= max(os.path.getmtime(SRC),
                                                                            os.path.getmtime(__file__)):
@@ -31,11 +36,14 @@ def _build_one(lib, defines, force):
     return lib
 
 
-def build(force=False, wide=False):
-    """Path of the narrow library (wide=False) or of the wide one."""
-    if wide:
-        return _build_one(LIB_WIDE, ["-DMAXL=%d" % MAXL_WIDE], force)
-    return _build_one(LIB, [], force)
+def build(force=False, wide=False, sanitize=False):
+    """Path of the narrow library (wide=False) or of the wide one; sanitize
+    gives the address / undefined-behaviour instrumented twin of either."""
+    lib, defines = (LIB_WIDE, ["-DMAXL=%d" % MAXL_WIDE]) if wide else (LIB, [])
+    if sanitize:
+        lib = lib.replace(".so", "_san.so")
+        defines = defines + SANITIZE
+    return _build_one(lib, defines, force)
 
 
 def build_all(force=False):

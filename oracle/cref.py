@@ -24,7 +24,9 @@ def lib(p=None, residual=False):
     need = 0 if p is None else (2 * (p // 32) + 2 if residual else p // 32)
     wide = need > NARROW_MAXL
     if wide not in _libs:
-        path = _build.build(wide=wide)
+        # MPREF_SANITIZE=1 loads the address / undefined-behaviour instrumented
+        # builds (the process must preload the sanitizer runtime)
+        path = _build.build(wide=wide, sanitize=os.environ.get("MPREF_SANITIZE") == "1")
         L = ctypes.CDLL(path)
         i64, i32, u32p, i32p = ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int32)
         L.ref_gemm.argtypes = [i64, i64, i64, i32, i32, i64, i32, i64,
