@@ -1,21 +1,25 @@
-"""Write the sampled full-size expected products used by the GPU parity tests.
+"""Write the full-size expected products used by the GPU parity tests.
 
 Calls only the CPU oracle (oracle.cref, the C twin of oracle/gemm.py) on the
 seeded synthetic inputs of paper_1410_1599_amd.inputs, computes each full
-product once, and stores a fixed sample of its entries:
+product once, and stores the sha256 of the whole result (its L + 2 planes as
+little-endian uint32, row-major, ld = n) and a fixed sample of its entries
+(for the message when a digest differs):
 
 * full_size_n1023_p256.json, full_size_n1024_p256.json: 256-bit products of
-  uniform (-1, 1) matrices (seeds 3 and 4), Strassen and Winograd with
-  cutoff 64 and odd sizes peeled;
+  uniform (-1, 1) matrices (seeds 3 and 4): Simple, Block (block 16),
+  Strassen and Winograd with cutoff 64 and odd sizes peeled;
 * full_size_n2048_p256.json: 2048 x 2048 at 256 bits, entries with
-  log-uniform magnitudes over 2^-21 .. 2^20 (seeds 6 and 7), Winograd and
-  Strassen with cutoff 64.
+  log-uniform magnitudes over 2^-21 .. 2^20 (seeds 6 and 7): Winograd,
+  Strassen and Simple with cutoff 64 (Block equals Simple bit for bit, an
+  oracle invariant pinned on the CPU).
 
 Entries are stored as [i, j, sign, exponent, mantissa hex].  Run from the
-repository root:  python tests/golden/make_full_size.py  (tens of minutes on
-eight cores).
+repository root:  python tests/golden/make_full_size.py [name ...]  (about an
+hour on eight cores for all three files).
 """
 
+import hashlib
 import json
 import os
 import sys
@@ -33,11 +37,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 CONFIGS = [
     dict(name="full_size_n1023_p256", n=1023, p=256, kind="uniform", seeds=(3, 4),
-         algos=("winograd", "strassen"), cutoff=64, policy="peel"),
+         algos=("winograd", "strassen", "simple", "block"), cutoff=64, policy="peel"),
     dict(name="full_size_n1024_p256", n=1024, p=256, kind="uniform", seeds=(3, 4),
-         algos=("winograd", "strassen"), cutoff=64, policy="peel"),
+         algos=("winograd", "strassen", "simple", "block"), cutoff=64, policy="peel"),
     dict(name="full_size_n2048_p256", n=2048, p=256, kind="log_uniform", seeds=(6, 7),
-         algos=("winograd", "strassen"), cutoff=64, policy="peel"),
+         algos=("winograd", "strassen", "simple"), cutoff=64, policy="peel"),
 ]
 
 
@@ -60,6 +64,10 @@ def sample_indices(n, seed=12345):
     return sorted(idx)
 
 
+def planes_sha256(C, n):
+    return hashlib.sha256(np.ascontiguousarray(C[:, :n, :n]).astype("<u4").tobytes()).hexdigest()
+
+
 def main(only=None):
     for cfg in CONFIGS:
         if only and cfg["name"] not in only:
@@ -67,8 +75,9 @@ def main(only=None):
         A, B = make_inputs(cfg)
         idx = sample_indices(cfg["n"])
         out = {k: v for k, v in cfg.items() if k != "algos"}
-        out["source"] = "oracle.cref.gemm (C oracle), sampled entries"
+        out["source"] = "oracle.cref.gemm (C oracle): sha256 of the whole result, and sampled entries"
         out["entries"] = {}
+        out["sha256"] = {}
         for algo in cfg["algos"]:
             t = time.time()
             C = cref.gemm(A, B, cfg["p"], algo=algo, cutoff=cfg["cutoff"], policy=cfg["policy"])
@@ -77,6 +86,7 @@ def main(only=None):
                 sig, e = I.entry(C, i, j, cfg["p"])
                 ents.append([i, j, 1 if sig < 0 else 0, e, "%x" % abs(sig)])
             out["entries"][algo] = ents
+            out["sha256"][algo] = planes_sha256(C, cfg["n"])
             print(cfg["name"], algo, "%.1fs" % (time.time() - t), flush=True)
         with open(os.path.join(HERE, cfg["name"] + ".json"), "w") as f:
             json.dump(out, f, separators=(",", ":"))
