@@ -296,7 +296,16 @@ template <int L>
 __device__ __forceinline__ MP<L> add_rn(const MP<L>& x, const MP<L>& y)
 {
     const bool zx = is_zero(x), zy = is_zero(y);
-    const bool ygt = (y.e > x.e) || (y.e == x.e && mant_less<L>(x.m, y.m));
+    // |y| > |x| for nonzero operands: the exponents, then the top limbs, and
+    // the whole mantissas only when some lane of the wave has both equal
+    const bool eqe = y.e == x.e;
+    bool mlt = x.m[L - 1] < y.m[L - 1];
+    const bool tie = eqe && (x.m[L - 1] == y.m[L - 1]);
+    if (__builtin_amdgcn_ballot_w64(tie) != 0) {
+        const bool full = mant_less<L>(x.m, y.m);
+        mlt = tie ? full : mlt;
+    }
+    const bool ygt = (y.e > x.e) || (eqe && mlt);
     const bool sw = zy ? false : (zx ? true : ygt);
     const MP<L> X = select(sw, y, x);
     const MP<L> Y = select(sw, x, y);
