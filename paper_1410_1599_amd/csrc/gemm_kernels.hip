@@ -197,7 +197,13 @@ k_node(const NodeTask* __restrict__ tasks, const int32_t* __restrict__ tile_task
         const int64_t e = (t - T.tile0) * NODE_TILE + threadIdx.x;
         const int64_t total = (int64_t)T.rows * T.cols;
         if (e >= total) continue;
-        node_apply<MP<L>, L, OP>(bs, T, e / T.cols, e % T.cols);
+        if (total <= (int64_t)0xffffffff) {       // 32-bit row and column (a 64-bit division costs ~170 VALU)
+            const uint32_t e32 = (uint32_t)e, c32 = (uint32_t)T.cols;
+            const uint32_t i32 = e32 / c32;
+            node_apply<MP<L>, L, OP>(bs, T, i32, e32 - i32 * c32);
+        } else {
+            node_apply<MP<L>, L, OP>(bs, T, e / T.cols, e % T.cols);
+        }
     }
 }
 
