@@ -122,64 +122,142 @@ k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ ti
 
 // ------------------------------------------------------------------ Block (LDS tiles)
 
+// global_load_lds_dword: each lane's word at src goes to LDS at lds + 4 * lane,
+// without passing through registers.  Issued through asm so that the compiler,
+// which cannot see the LDS write, leaves the waiting to the kernel's explicit
+// vmcnt wait before its barrier (the instruction has no register result).
+__device__ __forceinline__ void lds_dma4(const uint32_t* src, uint32_t lds)
+{
+    asm volatile("s_mov_b32 m0, %1\n\t"
+                 "s_nop 0\n\t"
+                 "global_load_lds_dword %0, off"
+                 :
+                 : "v"(src), "s"(lds)
+                 : "m0", "memory");
+}
+
+// a value the whole wave holds, moved to scalar registers
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t lds_addr32(const uint32_t* p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t*)p;
+}
+
+// Block (eq. (2)): a workgroup of TM waves owns TM rows x 64 columns and
+// walks k in blocks of TK.  Both operands' k-blocks are staged in LDS, double
+// buffered: B's TK x 64 elements (every plane), read there by all TM waves
+// instead of every wave fetching its own copy, and A's TM x TK elements.  The
+// staging is the asynchronous global-to-LDS copy, one instruction per 64
+// words: B's row-planes (64 consecutive words each) and A's block in chunks
+// of 64 (lane t fetches one word of one element) are dealt out over the
+// waves, and one barrier per block both publishes block kb and retires the
+// buffer that block kb + 1 then overwrites.  The inner loop touches LDS only,
+// so the next block's copies stay in flight during the products (a global
+// load there would make the compiler's wait for it also wait for them).
+// Every element keeps Simple's order (k ascending from exact zero), so Block
+// is bit-identical to Simple.
 template <int L, int TM, int TK>
 __global__ void __launch_bounds__(64 * TM)
 k_gemm_block(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
 {
-    constexpr int W = L + 2;                  // words per element
-    __shared__ uint32_t sB[TK][W][64];        // B tile, limb-major so lanes read consecutive words
-    __shared__ uint32_t sA[TM][TK][W];        // A tile, one row per wave (broadcast reads)
+    constexpr int W = L + 2;                  // words (planes) per element
+    constexpr int ROWS = TK * W;              // B: row-planes of one k-block
+    constexpr int AW = TM * TK * W;           // A: words of one k-block
+    constexpr int NA = (AW + 63) / 64;        // A: 64-word chunks
+    __shared__ uint32_t sB[2][TK][W][64];     // limb-major: a wave reads 64 consecutive words per plane
+    __shared__ uint32_t sA[2][NA * 64];       // word (r * TK + kk) * W + q: row i0 + r, k kb * TK + kk, plane q
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int nt = 64 * TM;
+    // the wave's index, as a scalar for the copy loop, and as a lane value
+    // for everything the products touch: A's element read through a scalar
+    // index is known to be uniform, and the compiler then moves parts of the
+    // product to scalar code (measured: 11% more vector and four times the
+    // scalar instructions per multiply-add)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
     for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
         const GemmTask T = tasks[tile_task[t]];
         const int64_t lt = t - T.tile0;
         const int tn = (T.n + 63) >> 6;
         const int64_t i0 = (lt / tn) * TM;
         const int64_t j0 = (lt % tn) * 64;
-        const int64_t i = i0 + w, j = j0 + lane;
-        const bool live = (i < T.m) && (j < T.n);
+        const int64_t i = i0 + wv, j = j0 + lane;
+        const bool row_live = i < T.m;        // uniform in the wave
+        const bool live = row_live && (j < T.n);
         const uint32_t* A = ref_ptr<L>(bs, T.A);
-        const uint32_t* B = ref_ptr<L>(bs, T.B);
+        // lanes past the last column copy the last column (their results are dropped)
+        const uint32_t* Bc = ref_ptr<L>(bs, T.B) + (j < T.n ? j : T.n - 1);
         uint32_t* C = base_ptr(bs, T.C.base) + T.C.off;
         MP<L> c = (T.accum && live) ? load<L>(C + i * T.C.ld + j, T.C.ps, 0) : mp_zero<L>();
-        for (int k0 = 0; k0 < T.l; k0 += TK) {
-            __syncthreads();
-            // stage B[k0 .. k0+TK) x [j0 .. j0+64): zero outside the product
-            for (int e = threadIdx.x; e < TK * 64 * W; e += nt) {
-                const int col = e & 63;
-                const int rest = e >> 6;
-                const int word = rest % W;
-                const int kk = rest / W;
-                const int64_t k = k0 + kk, jj = j0 + col;
-                uint32_t v = 0;
-                if (k < T.l && jj < T.n) v = B[word * T.B.ps + k * T.B.ld + jj];
-                sB[kk][word][col] = v;
-            }
-            for (int e = threadIdx.x; e < TM * TK * W; e += nt) {
-                const int word = e % W;
-                const int kk = (e / W) % TK;
-                const int r = e / (W * TK);
-                const int64_t k = k0 + kk, ii = i0 + r;
-                uint32_t v = 0;
-                if (k < T.l && ii < T.m) v = A[word * T.A.ps + ii * T.A.ld + k];
-                sA[r][kk][word] = v;
-            }
-            __syncthreads();
-            const int kn = (T.l - k0) < TK ? (T.l - k0) : TK;
-            for (int kk = 0; kk < kn; kk++) {
-                MP<L> a, b;
+        const int nkb = (T.l + TK - 1) / TK;
+        // A's copy addresses for this tile: wave w copies chunks w, w + TM,
+        // ...; lane t of chunk ch fetches word u = 64 ch + t of the block,
+        // row i0 + u / (TK W), k-offset kk = (u / W) mod TK, plane u mod W.
+        // Rows past m fetch row m - 1 (the products never read them).
+        constexpr int CPW = (NA + TM - 1) / TM;
+        const uint32_t* ap[CPW];
+        int akk[CPW];
 #pragma unroll
-                for (int q = 0; q < L; q++) {
-                    a.m[q] = sA[w][kk][q];
-                    b.m[q] = sB[kk][q][lane];
+        for (int s = 0; s < CPW; s++) {
+            const int u = (w + s * TM) * 64 + lane;
+            const int rr = u / (TK * W), v = u - rr * (TK * W);
+            const int kk = v / W, q = v - kk * W;
+            int64_t row = i0 + (rr < TM ? rr : TM - 1);
+            row = row < T.m ? row : T.m - 1;
+            ap[s] = A + q * T.A.ps + row * T.A.ld;
+            akk[s] = kk;
+        }
+        // the copies of block kb: B's k-rows w, w + TM, ... (all W planes,
+        // one scalar stride apart), then A's chunks; k past l fetches k = l - 1
+        auto issue = [&](int kb) {
+            const int buf = kb & 1;
+            const int64_t k0 = (int64_t)kb * TK;
+            for (int kk = w; kk < TK; kk += TM) {
+                if (k0 + kk < T.l) {
+                    const uint32_t* src = Bc + uniform64((k0 + kk) * T.B.ld);
+                    const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_addr32(&sB[buf][kk][0][0]));
+#pragma unroll
+                    for (int q = 0; q < W; q++) lds_dma4(src + q * T.B.ps, dst + q * 256);
                 }
-                a.e = (int32_t)sA[w][kk][L];
-                a.s = sA[w][kk][L + 1];
-                b.e = (int32_t)sB[kk][L][lane];
-                b.s = sB[kk][L + 1][lane];
-                c = add_rn<L>(c, mul_rn<L>(a, b));
+            }
+#pragma unroll
+            for (int s = 0; s < CPW; s++) {
+                const int ch = w + s * TM;
+                if (ch < NA) {
+                    int64_t k = k0 + akk[s];
+                    k = k < T.l ? k : T.l - 1;
+                    lds_dma4(ap[s] + k, __builtin_amdgcn_readfirstlane(lds_addr32(&sA[buf][ch * 64])));
+                }
+            }
+        };
+        __syncthreads();                      // the previous tile's reads of both buffers are done
+        if (nkb > 0) issue(0);
+        for (int kb = 0; kb < nkb; kb++) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies have landed
+            __syncthreads();                  // every wave's copies of block kb; block kb - 1 retired
+            if (kb + 1 < nkb) issue(kb + 1);
+            if (row_live) {
+                const int buf = kb & 1;
+                const int kn = (T.l - kb * TK) < TK ? (T.l - kb * TK) : TK;
+                for (int kk = 0; kk < kn; kk++) {
+                    const uint32_t* sa = &sA[buf][(wv * TK + kk) * W];
+                    MP<L> a, b;
+#pragma unroll
+                    for (int q = 0; q < L; q++) {
+                        a.m[q] = sa[q];
+                        b.m[q] = sB[buf][kk][q][lane];
+                    }
+                    a.e = (int32_t)sa[L];
+                    a.s = sa[L + 1];
+                    b.e = (int32_t)sB[buf][kk][L][lane];
+                    b.s = sB[buf][kk][L + 1][lane];
+                    c = add_rn<L>(c, mul_rn<L>(a, b));
+                }
             }
         }
         if (live) store<L>(C + i * T.C.ld + j, T.C.ps, 0, c);
@@ -366,9 +444,9 @@ static hipError_t gemm_launch_L(int kind, const GemmTask* tasks, const int32_t* 
 {
     if (ntiles <= 0) return hipSuccess;
     if (kind == LEAF_BLOCK) {
-        const dim3 g((unsigned)launch_grid(k_gemm_block<L, GEMM_TM, BLOCK_TK>, 64 * GEMM_TM, ntiles, grid));
-        hipLaunchKernelGGL((k_gemm_block<L, GEMM_TM, BLOCK_TK>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles,
-                           bs);
+        constexpr int TK = block_tk(L);
+        const dim3 g((unsigned)launch_grid(k_gemm_block<L, GEMM_TM, TK>, 64 * GEMM_TM, ntiles, grid));
+        hipLaunchKernelGGL((k_gemm_block<L, GEMM_TM, TK>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles, bs);
     } else {
         const dim3 g((unsigned)launch_grid(k_gemm_simple<L, GEMM_TM>, 64 * GEMM_TM, ntiles, grid));
         hipLaunchKernelGGL((k_gemm_simple<L, GEMM_TM>), g, dim3(64 * GEMM_TM), 0, s, tasks, tile_task, ntiles, bs);

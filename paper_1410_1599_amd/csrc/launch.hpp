@@ -9,7 +9,10 @@
 namespace mpg {
 
 constexpr int GEMM_TM = 4;          // rows (waves) per workgroup of a leaf product
-constexpr int BLOCK_TK = 8;         // k-depth of one LDS stage of the Block kernel
+// k-depth of one LDS stage of the Block kernel: two stages of B's 4 x 64 and
+// A's 4 x 4 elements are 22 KB at 256 bits (seven workgroups fit a CU's LDS),
+// 39 KB at 512, 74 KB at 1024
+constexpr int block_tk(int L) { return (void)L, 4; }
 
 enum LeafKind { LEAF_SIMPLE = 0, LEAF_BLOCK = 1 };
 
