@@ -37,16 +37,38 @@ hipError_t launch_fill_i32(int32_t* X, int64_t count, int32_t value, hipStream_t
 // search == 0: no row exchange, the pivot is a_cc
 hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
                                 int32_t* piv, int32_t* info, int search, hipStream_t s);
-// next: 0 plain; 1 also store each row's key of its new a_i,c+1 in keys[i - c
-// - 1] (n 64-bit words) for launch_lu_pivot_keys of column c + 1 < je; 2 also
-// check a_c+1,c+1 for the unpivoted LU.  Precisions of 2048 bits and more
-// take next = 0 only.
-hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, int32_t* piv,
-                               int32_t* info, unsigned long long* keys, int next, hipStream_t s);
-// pivot search of column c from the keys left by the elimination of column
-// c - 1, then the swap inside the panel [j0, je); below 2048 bits only
-hipError_t launch_lu_pivot_keys(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
-                                int32_t* piv, int32_t* info, const unsigned long long* keys, hipStream_t s);
+// Copies of the panel that the column steps leave for the next one (row
+// exchanges, below 2048 bits): after the step of column c - 1, keys_in[pos] is
+// the 64-bit key (exponent, top limb; 0 for zero) of a_pos,c and the panel
+// columns [c, je) of row pos are also in cand_in (plane q at cand + q cps +
+// pos cld + (j - j0), cld >= the panel width), for pos in [c, n); cmax_in[g]
+// is the largest key of the rows [c + 4 g, c + 4 g + 4) (a column step's
+// workgroup).  The step of column c reads the _in set and writes the _out
+// set; the caller alternates two sets (n keys, nch = ceil(n / 4) maxima and
+// (L + 2) cld n words each).
+struct PanelCopy {
+    const unsigned long long* keys_in;
+    const uint32_t* cand_in;
+    const unsigned long long* cmax_in;
+    unsigned long long* keys_out;
+    uint32_t* cand_out;
+    unsigned long long* cmax_out;
+    int64_t cps, cld, nch;
+};
+// The step of column c of the panel [j0, je): multipliers of the rows below c
+// and the panel's rank-one update.  next: 0 plain; 1 also write the _out copy
+// for column c + 1 < je; 2 also check a_c+1,c+1 for the unpivoted LU.
+// fused (c > j0, next != 2): the pivot search of column c and the exchange of
+// rows c and r inside the panel happen in the same launch, from the _in copy
+// (otherwise launch_lu_pivot_swap has done them).  Precisions of 2048 bits
+// and more take next = 0 and fused = 0 only.
+hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                               int32_t* piv, int32_t* info, const PanelCopy& pc, int next, int fused, hipStream_t s);
+// the pivot step of a column c > j0 from the _in copy, and the exchange of
+// rows c and r inside the panel, as a launch of its own (then
+// launch_lu_eliminate with fused = 0)
+hipError_t launch_lu_pivot_copy(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                                int32_t* piv, int32_t* info, const PanelCopy& pc, hipStream_t s);
 hipError_t launch_lu_u12(int L, const Bases& bs, MatRef a, int64_t j0, int64_t kb, int64_t je, int64_t n,
                          hipStream_t s);
 // piv[k0 .. k1) applied in order to the columns [c0, c1) and [c2, c3)

@@ -38,18 +38,24 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
     int rc = MP_OK;
     const int64_t m2max = n > panel ? n - panel : 0;
     const size_t pwords = (size_t)(L + 2) * (size_t)(m2max * m2max);
-    // aux buffer: the trailing product P, one int32 status word and the n
-    // 64-bit pivot keys of the column steps ((L + 2) is even, so the keys are
-    // 8-byte aligned)
-    uint32_t* aux = workspace(pwords + 64 + 2 * (size_t)n, s, WS_LU, &rc);
+    // below 2048 bits the step of column c leaves the keys and a copy of the
+    // panel rows for column c + 1 (or, unpivoted, checks its diagonal), and
+    // the pivot search of a later column of the panel runs inside its step
+    const bool keyed = L < 64;
+    const int64_t cld = keyed && pivot ? (panel < n ? panel : n) : 0;
+    const size_t cwords = (size_t)(L + 2) * (size_t)n * (size_t)cld;
+    const int64_t nch = (n + 3) / 4;
+    // aux buffer: the trailing product P, one int32 status word, two sets of
+    // n 64-bit keys and nch group maxima, and two panel copies ((L + 2) is
+    // even, so the keys are 8-byte aligned)
+    uint32_t* aux = workspace(pwords + 64 + 4 * (size_t)n + 4 * (size_t)nch + 2 * cwords, s, WS_LU, &rc);
     if (rc) return rc;
     int32_t* status = info_dev ? info_dev : (int32_t*)(aux + pwords);
-    unsigned long long* keys = (unsigned long long*)(aux + pwords + 64);
+    unsigned long long* k64 = (unsigned long long*)(aux + pwords + 64);
+    unsigned long long* keys[2] = {k64, k64 + n};
+    unsigned long long* cmax[2] = {k64 + 2 * n, k64 + 2 * n + nch};
+    uint32_t* cand[2] = {(uint32_t*)(k64 + 2 * n + 2 * nch), (uint32_t*)(k64 + 2 * n + 2 * nch) + cwords};
     MPG_TRY(launch_fill_i32(status, 1, 0, s));
-    // below 2048 bits the elimination of column c leaves the keys of column
-    // c + 1 (or, unpivoted, checks its diagonal), so a pivot step inside a
-    // panel reads the keys instead of the column
-    const bool keyed = L < 64;
     Bases bs{};
     bs.p[BASE_A] = A;
     const MatRef a{BASE_A, 0, 0, lda, psa};
@@ -59,13 +65,18 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
         for (int64_t c = j0; c < je; c++) {
             // pivot search and the swap inside the panel; then multipliers and
             // the panel's rank-one update (a zero pivot leaves a zero column, whose
-            // quotients and updates are exact no-ops)
-            if (c == j0 || !keyed)
-                MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, pivot, s));
-            else if (pivot)
-                MPG_TRY(launch_lu_pivot_keys(L, bs, a, n, c, j0, je, piv, status, keys, s));
+            // quotients and updates are exact no-ops).  Keyed and pivoted, a
+            // later step of the panel takes its pivot from the copy the step
+            // before left, inside its own launch up to 512 bits (at 1024 the
+            // column step has no registers to spare: a launch of its own).
+            const bool later = keyed && pivot && c > j0, fused = later && L <= 16;
             const int next = (keyed && c + 1 < je) ? (pivot ? 1 : 2) : 0;
-            MPG_TRY(launch_lu_eliminate(L, bs, a, n, c, je, piv, status, keys, next, s));
+            const int in = (int)((c - j0) & 1), out = in ^ 1;
+            const PanelCopy pc{keys[in],  cand[in],  cmax[in],         keys[out], cand[out],
+                               cmax[out], (int64_t)n * cld, cld, nch};
+            if (c == j0 || !keyed) MPG_TRY(launch_lu_pivot_swap(L, bs, a, n, c, j0, je, piv, status, pivot, s));
+            else if (later && !fused) MPG_TRY(launch_lu_pivot_copy(L, bs, a, n, c, j0, je, piv, status, pc, s));
+            MPG_TRY(launch_lu_eliminate(L, bs, a, n, c, j0, je, piv, status, pc, next, fused ? 1 : 0, s));
         }
         if (pivot) MPG_TRY(launch_lu_laswp(L, bs, a, piv, j0, je, 0, j0, je, n, s));
         if (je >= n) break;

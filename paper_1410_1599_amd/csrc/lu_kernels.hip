@@ -132,174 +132,250 @@ k_lu_pivot_swap(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je
     }
 }
 
-// The pivot of column c when the elimination of column c - 1 has left each
-// row's 64-bit key (exponent, top limb; 0 for zero) in keys[i - c] for the
-// rows i in [c, n): the keys are read coalesced, KR per thread at a time, and
-// the largest is found in LDS.  When one row holds it, that row is the pivot
-// (a nonzero key is a nonzero value); otherwise only the rows holding it have
-// their values read and compared in full (ascending, first index on ties) and
-// the pivot is settled as by the full search (a zero column: the first row,
-// info).  Then rows c and r are exchanged over the panel columns [j0, je).
-template <int L>
-__global__ void __launch_bounds__(PIV_THREADS)
-k_lu_pivot_keys(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info,
-                const unsigned long long* keys)
+// Wave-wide reductions (one-wave workgroups)
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 {
-    constexpr int NT = PIV_THREADS, KR = 4;
-    const int tid = threadIdx.x;
-    const int64_t m = n - c;
-    __shared__ unsigned long long smax;
-    if (tid == 0) smax = 0;
-    __syncthreads();
-    unsigned long long km = 0;
-    for (int64_t k0 = 0; k0 < m; k0 += KR * NT) {
-        unsigned long long kr[KR];
 #pragma unroll
-        for (int u = 0; u < KR; u++) {
-            const int64_t k = k0 + u * NT + tid;
-            kr[u] = k < m ? keys[k] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < KR; u++) km = kr[u] > km ? kr[u] : km;
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
     }
-    atomicMax(&smax, km);
-    __syncthreads();
-    const unsigned long long kmax = smax;
-    // the rows holding kmax: counted, and the smallest index kept
-    __shared__ int32_t scnt, sfirst;
-    if (tid == 0) {
-        scnt = 0;
-        sfirst = INT32_MAX;
-    }
-    __syncthreads();
-    for (int64_t k0 = 0; k0 < m; k0 += KR * NT) {
-        unsigned long long kr[KR];
-#pragma unroll
-        for (int u = 0; u < KR; u++) {
-            const int64_t k = k0 + u * NT + tid;
-            kr[u] = k < m ? keys[k] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < KR; u++) {
-            const int64_t k = k0 + u * NT + tid;
-            if (k < m && kr[u] == kmax) {
-                atomicAdd(&scnt, 1);
-                atomicMin(&sfirst, (int32_t)k);
-            }
-        }
-    }
-    __syncthreads();
-    int64_t r;
-    if (scnt == 1 && kmax != 0) {
-        // one row holds the largest key: it is the pivot, and nonzero
-        r = c + sfirst;
-        if (tid == 0) piv[c] = (int32_t)r;
-    } else {
-        // equal keys (or a zero column): compare the full values of those rows
-        int32_t best = -1;
-        MP<L> bv = mp_zero<L>();
-        for (int64_t k0 = 0; k0 < m; k0 += KR * NT) {
-            unsigned long long kr[KR];
-#pragma unroll
-            for (int u = 0; u < KR; u++) {
-                const int64_t k = k0 + u * NT + tid;
-                kr[u] = k < m ? keys[k] : 0ull;
-            }
-#pragma unroll
-            for (int u = 0; u < KR; u++) {
-                const int64_t k = k0 + u * NT + tid;
-                if (k < m && kr[u] == kmax) {
-                    const MP<L> v = ldm<L>(bs, a, c + k, c);
-                    if (best < 0 || cmp_abs<L>(v, bv) > 0) {
-                        best = (int32_t)(c + k);
-                        bv = v;
-                    }
-                }
-            }
-        }
-        r = settle_pivot<L, NT>(best, bv, c, piv, info);
-    }
-    if (r != c) swap_rows<L, NT>(bs, a, c, r, j0, je);
+    return v;
 }
 
-// One workgroup (one wave) per row i in (c, n): l = a_ic / a_cc by the whole
-// wave, one limb per lane (lanediv.hpp; the same bits as div_rn; the column
-// step at 512 bits drops from 13.7 to about 11 us), shared in LDS, then
-// a_ij := a_ij - l a_cj for the panel columns j in (c, je); a zero pivot skips
-// the column (no quotient, no update).
+__device__ __forceinline__ long long wave_min_i64(long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const long long w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+constexpr int ELIM_ROWS = 4;      // rows (one wave each) per workgroup of a column step
+
+// Several rows hold the largest key km (the first is row first): compare
+// their values from the copy in full, ascending, first index on ties.
+template <int L>
+__device__ long long settle_equal_keys(const PanelCopy& pc, int64_t n, int64_t c, int64_t j0,
+                                       unsigned long long km, long long first)
+{
+    long long bi = -1;
+    MP<L> bx = mp_zero<L>();
+    for (int64_t k = first; k < n; k++) {
+        if (pc.keys_in[k] != km) continue;
+        const MP<L> v = load<L>(pc.cand_in, pc.cps, k * pc.cld + (c - j0));
+        if (bi < 0 || cmp_abs<L>(v, bx) > 0) {
+            bi = k;
+            bx = v;
+        }
+    }
+    return bi;
+}
+
+// The pivot of column c from the keys the step of column c - 1 left
+// (PanelCopy), found by the calling wave alone (every lane gets it): the
+// largest key over the rows [c, n), from the maxima of the groups of
+// ELIM_ROWS rows; when one row holds it (one group, and one row of that
+// group), that row (a nonzero key is a nonzero value); when several do,
+// their values (from the copy) are compared in full, ascending, first index
+// on ties; a zero column gives the first row and *zero.  The same choice as
+// the full search of pivot_and_swap.  A wave reads the group maxima and one
+// group's keys, not all n - c keys.
+template <int L>
+__device__ int64_t find_pivot(const PanelCopy& pc, int64_t n, int64_t c, int64_t j0, bool* zero)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t ng = (n - c + ELIM_ROWS - 1) / ELIM_ROWS;
+    unsigned long long km = 0;
+    for (int64_t g = lane; g < ng; g += 64) {
+        const unsigned long long v = pc.cmax_in[g];
+        km = v > km ? v : km;
+    }
+    km = wave_max_u64(km);
+    *zero = km == 0;
+    if (km == 0) return c;
+    long long fg = ng;
+    int cnt = 0;
+    for (int64_t g = lane; g < ng; g += 64)
+        if (pc.cmax_in[g] == km) {
+            fg = g < fg ? g : fg;
+            cnt++;
+        }
+    fg = wave_min_i64(fg);
+    cnt = wave_sum(cnt);
+    long long first = n;
+    {
+        // the rows of the first group holding the largest key
+        const int64_t k = c + fg * ELIM_ROWS + lane;
+        const bool hit = lane < ELIM_ROWS && k < n && pc.keys_in[k] == km;
+        const uint64_t hits = __builtin_amdgcn_ballot_w64(hit);
+        cnt += __builtin_popcountll(hits) - 1;
+        if (hits) first = c + fg * ELIM_ROWS + __builtin_ctzll(hits);
+    }
+    if (cnt == 1) return first;
+    long long bi = 0;
+    if (lane == 0) bi = settle_equal_keys<L>(pc, n, c, j0, km, first);
+    return __shfl(bi, 0);
+}
+
+// The pivot step of column c as a launch of its own (the precisions whose
+// column step has no registers to spare for the search): the pivot from the
+// copy (find_pivot), then rows c and r exchanged over the panel columns
+// [j0, je).
+template <int L>
+__global__ void __launch_bounds__(64)
+k_lu_pivot_copy(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info,
+                PanelCopy pc)
+{
+    bool zero_col;
+    const int64_t r = find_pivot<L>(pc, n, c, j0, &zero_col);
+    if (threadIdx.x == 0) {
+        piv[c] = (int32_t)r;
+        if (zero_col && info[0] == 0) info[0] = (int32_t)(c + 1);
+    }
+    if (r != c) swap_rows<L, 64>(bs, a, c, r, j0, je);
+}
+
+// The step of column c: one wave per row position pos in (c, n), ELIM_ROWS
+// of them per workgroup: l = a_pos,c / a_cc by the whole wave, one limb per
+// lane (lanediv.hpp; the same bits as div_rn), its limbs then read out of the
+// lanes, and a_pos,j := a_pos,j - l a_cj for the panel columns j in (c, je);
+// a zero pivot skips the column (no quotient, no update).
 //
-// next == ELIM_NEXT_KEYS (c + 1 < je): lane 0 of each workgroup, which has
-// just formed its row's new a_i,c+1, stores the row's 64-bit key (exponent,
-// top limb; 0 for zero) in keys[i - c - 1] for the pivot step of column c + 1.
+// FUSED (row exchanges, a step after the panel's first): the pivot search of
+// column c runs in the same launch.  Every wave finds the pivot row r from
+// the keys of the copy (find_pivot) and works as if rows c and r were
+// already exchanged: the pivot row (old row r) is read from the copy, never
+// from A, and the row at position r is old row c.  The wave of position r
+// also performs the exchange over the panel columns [j0, je): it is the only
+// one that touches positions c and r, so no wave reads what another writes.
+// Workgroup 0 records piv[c] and a zero pivot in info.
+//
+// next == ELIM_NEXT_KEYS (c + 1 < je): each wave stores its row's new
+// a_pos,c+1 key (exponent, top limb; 0 for zero) in keys_out[pos] and its
+// row's panel columns (c, je) in cand_out, and each workgroup the largest
+// key of its rows in cmax_out[blockIdx.x] (one plain store: an atomic
+// maximum over the workgroups sharing a word serialises in memory), for the
+// step of column c + 1.
 //
 // next == ELIM_NEXT_DIAG (no row exchanges): the owner of row c + 1 checks its
 // new a_c+1,c+1 for zero (info) and sets piv[c + 1] = c + 1.
-constexpr int ELIM_THREADS = 64;
+constexpr int ELIM_THREADS = 64 * ELIM_ROWS;
 constexpr int ELIM_PLAIN = 0, ELIM_NEXT_KEYS = 1, ELIM_NEXT_DIAG = 2;
 
-template <int L>
+template <int L, bool FUSED>
 __global__ void __launch_bounds__(ELIM_THREADS)
-k_lu_eliminate(Bases bs, MatRef a, int64_t c, int64_t je, int32_t* piv, int32_t* info, unsigned long long* keys,
-               int next)
+k_lu_eliminate(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je, int32_t* piv, int32_t* info,
+               PanelCopy pc, int next)
 {
-    static_assert(ELIM_THREADS == 64, "the division takes the one wave of the workgroup");
-    __shared__ uint32_t sl[L + 2];
-    const int tid = threadIdx.x;
-    const int64_t i = c + 1 + blockIdx.x;
-    // this lane's first pair of operands is loaded while the wave divides
-    const int64_t jf = c + 1 + tid;
-    const bool has = jf < je;
-    MP<L> xf = has ? ldm<L>(bs, a, i, jf) : mp_zero<L>();
-    const MP<L> uf = has ? ldm<L>(bs, a, c, jf) : mp_zero<L>();
-    // a_cc and a_ic in the lane layout: lane t holds limb t
-    const uint32_t* pa = base_ptr(bs, a.base) + a.off;
-    const int64_t idd = c * a.ld + c, idx = i * a.ld + c;
-    const uint32_t dm = tid < L ? pa[tid * a.ps + idd] : 0u;
-    const uint32_t xm = tid < L ? pa[tid * a.ps + idx] : 0u;
-    const int32_t de = (int32_t)pa[L * a.ps + idd], xe = (int32_t)pa[L * a.ps + idx];
-    const uint32_t dsg = pa[(L + 1) * a.ps + idd], xsg = pa[(L + 1) * a.ps + idx];
-    const bool skip = lane_limb<L>(dm, L - 1) == 0u;        // a zero pivot (uniform)
-    if (!skip) {
-        int32_t le;
-        uint32_t ls;
-        const uint32_t lm = lane_div_rn<L>(xm, xe, xsg, dm, de, dsg, &le, &ls);
-        uint32_t* pl = base_ptr(bs, a.base) + a.off;
-        if (tid < L) {
-            sl[tid] = lm;
-            pl[tid * a.ps + idx] = lm;
-        }
-        if (tid == 0) {
-            sl[L] = (uint32_t)le;
-            sl[L + 1] = ls;
-            pl[L * a.ps + idx] = (uint32_t)le;
-            pl[(L + 1) * a.ps + idx] = ls;
+    __shared__ unsigned long long skey[ELIM_ROWS];
+    const int tid = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t pos = c + 1 + (int64_t)blockIdx.x * ELIM_ROWS + w;
+    const bool keep = next == ELIM_NEXT_KEYS;
+    unsigned long long key = 0;
+    int64_t r = c;
+    if (FUSED) {
+        bool zero_col;
+        r = find_pivot<L>(pc, n, c, j0, &zero_col);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            piv[c] = (int32_t)r;
+            if (zero_col && info[0] == 0) info[0] = (int32_t)(c + 1);
         }
     }
-    __syncthreads();
-    if (!skip) {
-        MP<L> l;
+    if (pos < n) {
+        const bool swap = FUSED && pos == r;      // this row's content sits at position c
+        const int64_t src = swap ? c : pos;
+        uint32_t* pa = base_ptr(bs, a.base) + a.off;
+        // the pivot row: from the copy (FUSED) or row c of A
+        const uint32_t* pu = FUSED ? pc.cand_in : pa;
+        const int64_t ups = FUSED ? pc.cps : a.ps;
+        const int64_t u0 = FUSED ? r * pc.cld - j0 : c * a.ld;    // + j: element (pivot row, j)
+        // this lane's first pair of operands is loaded while the wave divides
+        const int64_t jf = c + 1 + tid;
+        const bool has = jf < je;
+        MP<L> xf = has ? ldm<L>(bs, a, src, jf) : mp_zero<L>();
+        const MP<L> uf = has ? load<L>(pu, ups, u0 + jf) : mp_zero<L>();
+        // the pivot and a_src,c in the lane layout: lane t holds limb t
+        const int64_t idd = u0 + c, idx = src * a.ld + c;
+        const uint32_t dm = tid < L ? pu[tid * ups + idd] : 0u;
+        const uint32_t xm = tid < L ? pa[tid * a.ps + idx] : 0u;
+        const int32_t de = (int32_t)pu[L * ups + idd], xe = (int32_t)pa[L * a.ps + idx];
+        const uint32_t dsg = pu[(L + 1) * ups + idd], xsg = pa[(L + 1) * a.ps + idx];
+        const bool skip = lane_limb<L>(dm, L - 1) == 0u;        // a zero pivot (uniform)
+        MP<L> l = mp_zero<L>();
+        if (!skip) {
+            int32_t le;
+            uint32_t ls;
+            const uint32_t lm = lane_div_rn<L>(xm, xe, xsg, dm, de, dsg, &le, &ls);
+            const int64_t idp = pos * a.ld + c;
+            if (tid < L) pa[tid * a.ps + idp] = lm;
+            if (tid == 0) {
+                pa[L * a.ps + idp] = (uint32_t)le;
+                pa[(L + 1) * a.ps + idp] = ls;
+            }
 #pragma unroll
-        for (int q = 0; q < L; q++) l.m[q] = sl[q];
-        l.e = (int32_t)sl[L];
-        l.s = sl[L + 1];
-        if (has) {
-            xf = sub_rn<L>(xf, mul_rn<L>(l, uf));
-            stm<L>(bs, a, i, jf, xf);
+            for (int q = 0; q < L; q++) l.m[q] = __builtin_amdgcn_readlane(lm, q);
+            l.e = le;
+            l.s = ls;
         }
-        for (int64_t j = jf + ELIM_THREADS; j < je; j += ELIM_THREADS)
-            stm<L>(bs, a, i, j, sub_rn<L>(ldm<L>(bs, a, i, j), mul_rn<L>(l, ldm<L>(bs, a, c, j))));
-    }
-    // lane 0 now holds the row's final a_i,c+1 in xf (column c+1 < je)
-    if (next == ELIM_NEXT_DIAG) {
-        if (tid == 0 && i == c + 1) {
+        const int64_t co = pos * pc.cld - j0;                    // + j: this row in cand_out
+        // a_pos,j from x (the row's content) and u (the pivot row's)
+        auto update = [&](const MP<L>& x, const MP<L>& u, int64_t j) __attribute__((always_inline)) -> MP<L> {
+            if (swap) stm<L>(bs, a, c, j, u);                    // row c := old row r (x is read)
+            const MP<L> y = skip ? x : sub_rn<L>(x, mul_rn<L>(l, u));
+            if (!skip || swap) stm<L>(bs, a, pos, j, y);
+            if (keep) store<L>(pc.cand_out, pc.cps, co + j, y);
+            return y;
+        };
+        if (has) xf = update(xf, uf, jf);
+        for (int64_t j = jf + 64; j < je; j += 64) update(ldm<L>(bs, a, src, j), load<L>(pu, ups, u0 + j), j);
+        if (swap) {
+            // the rest of the exchange: columns [j0, c) both ways, and the pivot
+            // into a_cc (a_rc got the quotient above)
+            for (int64_t j = j0 + tid; j < c; j += 64) {
+                const MP<L> x = ldm<L>(bs, a, c, j), v = ldm<L>(bs, a, r, j);
+                stm<L>(bs, a, c, j, v);
+                stm<L>(bs, a, r, j, x);
+            }
+            const int64_t idc = c * a.ld + c;
+            if (tid < L) pa[tid * a.ps + idc] = dm;
+            if (tid == 0) {
+                pa[L * a.ps + idc] = (uint32_t)de;
+                pa[(L + 1) * a.ps + idc] = dsg;
+            }
+        }
+        // lane 0 now holds the row's final a_pos,c+1 in xf (column c+1 < je)
+        if (next == ELIM_NEXT_DIAG && tid == 0 && pos == c + 1) {
             piv[c + 1] = (int32_t)(c + 1);
             if (is_zero<L>(xf) && info[0] == 0) info[0] = (int32_t)(c + 2);
         }
-        return;
+        if (keep && tid == 0) {
+            key = is_zero<L>(xf) ? 0ull
+                                 : (((unsigned long long)(uint32_t)(xf.e + (1 << 30)) << 32) | xf.m[L - 1]);
+            pc.keys_out[pos] = key;
+        }
     }
-    if (next == ELIM_NEXT_KEYS && tid == 0)
-        keys[blockIdx.x] =
-            is_zero<L>(xf) ? 0ull : (((unsigned long long)(uint32_t)(xf.e + (1 << 30)) << 32) | xf.m[L - 1]);
+    if (keep) {
+        // the largest key of the workgroup's rows (0 for rows past n)
+        if (tid == 0) skey[w] = key;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long m = 0;
+#pragma unroll
+            for (int k = 0; k < ELIM_ROWS; k++) m = skey[k] > m ? skey[k] : m;
+            pc.cmax_out[blockIdx.x] = m;
+        }
+    }
 }
 
 // U12 := L11^-1 A12: one workgroup per column j >= je, one lane per panel row;
@@ -351,9 +427,12 @@ k_lu_u12(Bases bs, MatRef a, int64_t j0, int64_t kb, int64_t je)
 // Apply the swaps piv[k0 .. k1) in order (k1 - k0 <= LASWP_MAXK) to the
 // columns [c0, c1) and [c2, c3).  The swaps only move the rows k0 .. k1 - 1
 // and the rows they name, so they form one permutation of at most
-// 2 (k1 - k0) "slots": one thread works it out in LDS (src[s] = the slot whose
-// old content ends in slot s), then each workgroup moves the changed slots of
-// one plane and LASWP_CW columns through LDS (all reads before all writes).
+// 2 (k1 - k0) "slots": slot t < kb is row k0 + t, slot kb + t the row piv[k0 +
+// t] when it lies past k1 and swap t is the first to name it (else unused).
+// Each thread works out src[s] (the slot whose old content ends in slot s)
+// for its slots by itself, following the swaps backwards from the slot's
+// row; then each workgroup moves the changed slots of one plane and
+// LASWP_CW columns through LDS (all reads before all writes).
 constexpr int LASWP_MAXK = 256, LASWP_MAXS = 2 * LASWP_MAXK, LASWP_CW = 16, LASWP_THREADS = 256;
 
 template <int L>
@@ -361,46 +440,49 @@ __global__ void __launch_bounds__(LASWP_THREADS)
 k_lu_laswp(Bases bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1, int64_t c0, int64_t c1, int64_t c2,
            int64_t c3)
 {
-    __shared__ int32_t rowof[LASWP_MAXS], src[LASWP_MAXS];
+    __shared__ int32_t rowof[LASWP_MAXS], src[LASWP_MAXS], pv[LASWP_MAXK];
     __shared__ uint32_t tile[LASWP_MAXS][LASWP_CW];
-    __shared__ int32_t s_ns;
-    if (threadIdx.x == 0) {
-        const int kb = (int)(k1 - k0);
-        int ns = kb;
-        for (int t = 0; t < kb; t++) {
-            rowof[t] = (int32_t)(k0 + t);
-            src[t] = t;
+    const int kb = (int)(k1 - k0);
+    const int ns = 2 * kb;
+    for (int t = threadIdx.x; t < kb; t += LASWP_THREADS) pv[t] = piv[k0 + t];   // pv[t] >= k0 + t
+    __syncthreads();
+    for (int sl = threadIdx.x; sl < ns; sl += LASWP_THREADS) {
+        int32_t row = -1;
+        if (sl < kb) {
+            row = (int32_t)(k0 + sl);
+        } else {
+            const int t = sl - kb;
+            const int32_t r = pv[t];
+            bool first = r >= k1;
+            for (int u = 0; u < t && first; u++) first = pv[u] != r;
+            if (first) row = r;
         }
-        for (int t = 0; t < kb; t++) {
-            const int64_t r = piv[k0 + t];   // r >= k0 + t by construction of the pivots
-            int sl;
-            if (r < k1) {
-                sl = (int)(r - k0);
-            } else {
-                sl = -1;
-                for (int u = kb; u < ns; u++)
-                    if (rowof[u] == r) sl = u;
-                if (sl < 0) {
-                    sl = ns++;
-                    rowof[sl] = (int32_t)r;
-                    src[sl] = sl;
-                }
+        int sv = sl;
+        if (row >= 0) {
+            int64_t x = row;                  // the old row whose content ends in this slot
+            for (int t = kb - 1; t >= 0; t--) {
+                if (x == k0 + t) x = pv[t];
+                else if (x == pv[t]) x = k0 + t;
             }
-            const int x = src[t];
-            src[t] = src[sl];
-            src[sl] = x;
+            if (x < k1) {
+                sv = (int)(x - k0);
+            } else {
+                int u = 0;
+                while (pv[u] != x) u++;       // x is named by some swap
+                sv = kb + u;
+            }
         }
-        s_ns = ns;
+        rowof[sl] = row;
+        src[sl] = sv;
     }
     __syncthreads();
-    const int ns = s_ns;
     const int64_t n1 = c1 - c0, nc = n1 + (c3 - c2);
     const int64_t cb = (int64_t)blockIdx.x * LASWP_CW;
     uint32_t* P = base_ptr(bs, a.base) + a.off + (int64_t)blockIdx.y * a.ps;
     for (int e = threadIdx.x; e < ns * LASWP_CW; e += LASWP_THREADS) {
         const int sl = e / LASWP_CW, jj = e % LASWP_CW;
         const int64_t ci = cb + jj;
-        if (ci < nc && src[sl] != sl) {
+        if (ci < nc && rowof[sl] >= 0 && src[sl] != sl) {
             const int64_t j = ci < n1 ? c0 + ci : c2 + (ci - n1);
             tile[sl][jj] = P[(int64_t)rowof[src[sl]] * a.ld + j];
         }
@@ -409,7 +491,7 @@ k_lu_laswp(Bases bs, MatRef a, const int32_t* piv, int64_t k0, int64_t k1, int64
     for (int e = threadIdx.x; e < ns * LASWP_CW; e += LASWP_THREADS) {
         const int sl = e / LASWP_CW, jj = e % LASWP_CW;
         const int64_t ci = cb + jj;
-        if (ci < nc && src[sl] != sl) {
+        if (ci < nc && rowof[sl] >= 0 && src[sl] != sl) {
             const int64_t j = ci < n1 ? c0 + ci : c2 + (ci - n1);
             P[(int64_t)rowof[sl] * a.ld + j] = tile[sl][jj];
         }
@@ -610,26 +692,53 @@ hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int
     return hipGetLastError();
 }
 
-hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t je, int32_t* piv,
-                               int32_t* info, unsigned long long* keys, int next, hipStream_t s)
+hipError_t launch_lu_eliminate(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                               int32_t* piv, int32_t* info, const PanelCopy& pc, int next, int fused, hipStream_t s)
 {
-    if (n - c - 1 <= 0) return hipSuccess;
-    if (next != ELIM_PLAIN && (c + 1 >= je || (next == ELIM_NEXT_KEYS && !keys))) return hipErrorInvalidValue;
+    if (c < j0 || c >= je || je > n) return hipErrorInvalidValue;
+    if (next != ELIM_PLAIN && c + 1 >= je) return hipErrorInvalidValue;
+    const int64_t nch = (n + ELIM_ROWS - 1) / ELIM_ROWS;
+    if (next == ELIM_NEXT_KEYS && (!pc.keys_out || !pc.cand_out || !pc.cmax_out || pc.cld < je - j0 ||
+                                   pc.nch != nch))
+        return hipErrorInvalidValue;
+    if (fused && (c == j0 || !pc.keys_in || !pc.cand_in || !pc.cmax_in || pc.cld < je - j0 || pc.nch != nch ||
+                  next == ELIM_NEXT_DIAG))
+        return hipErrorInvalidValue;
     if (L >= 64) {
-        if (next != ELIM_PLAIN) return hipErrorInvalidValue;
+        if (next != ELIM_PLAIN || fused) return hipErrorInvalidValue;
+        if (n - c - 1 <= 0) return hipSuccess;
         return launch_lu_eliminate_wide(L, bs, a, n, c, je, s);
     }
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_eliminate<LL>), dim3((unsigned)(n - c - 1)), dim3(ELIM_THREADS), 0, s,
-                                         bs, a, c, je, piv, info, keys, next));
+    const int64_t rows = n - c - 1, ng = (rows + ELIM_ROWS - 1) / ELIM_ROWS;
+    if (fused) {
+        // one workgroup at least: it records the pivot of the last column
+        // (up to 512 bits: at 1024 the step has no registers to spare for
+        // the search, and launch_lu_pivot_copy runs it)
+        const dim3 g((unsigned)(ng > 0 ? ng : 1)), b(ELIM_THREADS);
+        switch (L) {
+        case 4: hipLaunchKernelGGL((k_lu_eliminate<4, true>), g, b, 0, s, bs, a, n, c, j0, je, piv, info, pc, next); break;
+        case 8: hipLaunchKernelGGL((k_lu_eliminate<8, true>), g, b, 0, s, bs, a, n, c, j0, je, piv, info, pc, next); break;
+        case 16:
+            hipLaunchKernelGGL((k_lu_eliminate<16, true>), g, b, 0, s, bs, a, n, c, j0, je, piv, info, pc, next);
+            break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        if (rows <= 0) return hipSuccess;
+        MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_eliminate<LL, false>), dim3((unsigned)ng), dim3(ELIM_THREADS), 0,
+                                             s, bs, a, n, c, j0, je, piv, info, pc, next));
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_lu_pivot_keys(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
-                                int32_t* piv, int32_t* info, const unsigned long long* keys, hipStream_t s)
+hipError_t launch_lu_pivot_copy(int L, const Bases& bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
+                                int32_t* piv, int32_t* info, const PanelCopy& pc, hipStream_t s)
 {
-    if (L >= 64 || !keys || c >= n) return hipErrorInvalidValue;
-    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_pivot_keys<LL>), dim3(1), dim3(PIV_THREADS), 0, s, bs, a, n, c, j0, je,
-                                         piv, info, keys));
+    if (L >= 64 || c <= j0 || c >= je || je > n || !pc.keys_in || !pc.cand_in || !pc.cmax_in ||
+        pc.cld < je - j0 || pc.nch != (n + ELIM_ROWS - 1) / ELIM_ROWS)
+        return hipErrorInvalidValue;
+    MPG_DISPATCH_L(L, hipLaunchKernelGGL((k_lu_pivot_copy<LL>), dim3(1), dim3(64), 0, s, bs, a, n, c, j0, je, piv,
+                                         info, pc));
     return hipGetLastError();
 }
 

@@ -108,6 +108,20 @@ def test_lu_many_rows_per_pivot_step():
     assert planes_equal(gpu_solve(Fg, pg, b, p), cref.lu_solve(Fc, pc, b, p))
 
 
+@pytest.mark.parametrize("p,n,panel", [(256, 230, 100), (1024, 90, 70), (128, 131, 131)])
+def test_lu_panels_wider_than_a_wave(p, n, panel):
+    """Panels wider than 64 columns: each lane of a column step updates several
+    columns, and the row exchange inside the step moves several columns per
+    lane on both sides of the pivot column; one panel may span the matrix."""
+    A = I.uniform_pm1(n, n, p, 17)
+    Fc, pc, ic = cref.lu(A, p, panel=panel, algo="winograd", cutoff=16)
+    Fg, pg, ig = gpu_lu(A, p, panel, mp.WINOGRAD, 16)
+    assert ig == ic == 0
+    assert list(pg) == list(pc)
+    assert sum(int(pc[k]) != k for k in range(n)) > n // 2      # rows do move
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+
+
 @pytest.mark.parametrize("kind", ["random", "hilbert"])
 def test_lu_n512_p512_panel64_winograd(kind):
     """The LU workload: n = 512, 512 bits, panel 64, Winograd trailing
