@@ -41,11 +41,12 @@ hipError_t launch_lu_pivot_swap(int L, const Bases& bs, MatRef a, int64_t n, int
 // exchanges, below 2048 bits): after the step of column c - 1, keys_in[pos] is
 // the 64-bit key (exponent, top limb; 0 for zero) of a_pos,c and the panel
 // columns [c, je) of row pos are also in cand_in (plane q at cand + q cps +
-// pos cld + (j - j0), cld >= the panel width), for pos in [c, n); cmax_in[g]
-// is the largest key of the rows [c + 4 g, c + 4 g + 4) (a column step's
-// workgroup).  The step of column c reads the _in set and writes the _out
-// set; the caller alternates two sets (n keys, nch = ceil(n / 4) maxima and
-// (L + 2) cld n words each).
+// pos cld + (j - j0), cld >= the panel width), for pos in [c, n); for the
+// rows [c + 4 g, c + 4 g + 4) (a column step's workgroup) cmax_in[2 g] is
+// their largest key and cmax_in[2 g + 1] the first of them holding it, plus
+// 2^63 when another does.  The step of column c reads the _in set and writes
+// the _out set; the caller alternates two sets (n keys, nch = ceil(n / 4)
+// two-word records and (L + 2) cld n words each).
 struct PanelCopy {
     const unsigned long long* keys_in;
     const uint32_t* cand_in;

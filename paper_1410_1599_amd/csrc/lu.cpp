@@ -46,15 +46,15 @@ int lu_run(int64_t n, int L, uint32_t* A, int64_t lda, int64_t psa, int32_t* piv
     const size_t cwords = (size_t)(L + 2) * (size_t)n * (size_t)cld;
     const int64_t nch = (n + 3) / 4;
     // aux buffer: the trailing product P, one int32 status word, two sets of
-    // n 64-bit keys and nch group maxima, and two panel copies ((L + 2) is
-    // even, so the keys are 8-byte aligned)
-    uint32_t* aux = workspace(pwords + 64 + 4 * (size_t)n + 4 * (size_t)nch + 2 * cwords, s, WS_LU, &rc);
+    // n 64-bit keys and nch two-word group records, and two panel copies
+    // ((L + 2) is even, so the keys are 8-byte aligned)
+    uint32_t* aux = workspace(pwords + 64 + 4 * (size_t)n + 8 * (size_t)nch + 2 * cwords, s, WS_LU, &rc);
     if (rc) return rc;
     int32_t* status = info_dev ? info_dev : (int32_t*)(aux + pwords);
     unsigned long long* k64 = (unsigned long long*)(aux + pwords + 64);
     unsigned long long* keys[2] = {k64, k64 + n};
-    unsigned long long* cmax[2] = {k64 + 2 * n, k64 + 2 * n + nch};
-    uint32_t* cand[2] = {(uint32_t*)(k64 + 2 * n + 2 * nch), (uint32_t*)(k64 + 2 * n + 2 * nch) + cwords};
+    unsigned long long* cmax[2] = {k64 + 2 * n, k64 + 2 * n + 2 * nch};
+    uint32_t* cand[2] = {(uint32_t*)(k64 + 2 * n + 4 * nch), (uint32_t*)(k64 + 2 * n + 4 * nch) + cwords};
     MPG_TRY(launch_fill_i32(status, 1, 0, s));
     Bases bs{};
     bs.p[BASE_A] = A;

@@ -181,49 +181,58 @@ __device__ long long settle_equal_keys(const PanelCopy& pc, int64_t n, int64_t c
     return bi;
 }
 
-// The pivot of column c from the keys the step of column c - 1 left
+// The pivot of column c from the copy the step of column c - 1 left
 // (PanelCopy), found by the calling wave alone (every lane gets it): the
-// largest key over the rows [c, n), from the maxima of the groups of
-// ELIM_ROWS rows; when one row holds it (one group, and one row of that
-// group), that row (a nonzero key is a nonzero value); when several do,
-// their values (from the copy) are compared in full, ascending, first index
-// on ties; a zero column gives the first row and *zero.  The same choice as
-// the full search of pivot_and_swap.  A wave reads the group maxima and one
-// group's keys, not all n - c keys.
+// largest key over the rows [c, n), from the groups of ELIM_ROWS rows (each
+// group's largest key, the first of its rows holding it, and whether another
+// does); when one row holds it (one group, and one row of that group), that
+// row (a nonzero key is a nonzero value); when several do, their values
+// (from the copy) are compared in full, ascending, first index on ties; a
+// zero column gives the first row and *zero.  The same choice as the full
+// search of pivot_and_swap, from one round of loads of the group records.
 template <int L>
 __device__ int64_t find_pivot(const PanelCopy& pc, int64_t n, int64_t c, int64_t j0, bool* zero)
 {
     const int lane = threadIdx.x & 63;
     const int64_t ng = (n - c + ELIM_ROWS - 1) / ELIM_ROWS;
-    unsigned long long km = 0;
+    // this lane's groups g = lane, lane + 64, ...: the largest key, how many
+    // of them hold it, and the first one's record
+    constexpr long long NONE = 0x7fffffffffffffffll;
+    unsigned long long km = 0, finfo = 0;
+    long long fg = NONE;
+    int hold = 0;
     for (int64_t g = lane; g < ng; g += 64) {
-        const unsigned long long v = pc.cmax_in[g];
-        km = v > km ? v : km;
-    }
-    km = wave_max_u64(km);
-    *zero = km == 0;
-    if (km == 0) return c;
-    long long fg = ng;
-    int cnt = 0;
-    for (int64_t g = lane; g < ng; g += 64)
-        if (pc.cmax_in[g] == km) {
-            fg = g < fg ? g : fg;
-            cnt++;
+        const unsigned long long v = pc.cmax_in[2 * g], f = pc.cmax_in[2 * g + 1];
+        if (fg == NONE || v > km) {
+            km = v;
+            fg = g;
+            finfo = f;
+            hold = 1;
+        } else if (v == km) {
+            hold++;
         }
-    fg = wave_min_i64(fg);
-    cnt = wave_sum(cnt);
-    long long first = n;
-    {
-        // the rows of the first group holding the largest key
-        const int64_t k = c + fg * ELIM_ROWS + lane;
-        const bool hit = lane < ELIM_ROWS && k < n && pc.keys_in[k] == km;
-        const uint64_t hits = __builtin_amdgcn_ballot_w64(hit);
-        cnt += __builtin_popcountll(hits) - 1;
-        if (hits) first = c + fg * ELIM_ROWS + __builtin_ctzll(hits);
     }
-    if (cnt == 1) return first;
+    const unsigned long long kmax = wave_max_u64(km);
+    *zero = kmax == 0;
+    if (kmax == 0) return c;
+    if (km != kmax) {
+        fg = NONE;
+        hold = 0;
+    }
+    hold = wave_sum(hold);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const long long og = __shfl_xor(fg, o);
+        const unsigned long long oi = __shfl_xor(finfo, o);
+        if (og < fg) {
+            fg = og;
+            finfo = oi;
+        }
+    }
+    const long long first = (long long)(finfo & 0x7fffffffffffffffull);
+    if (hold == 1 && (finfo >> 63) == 0) return first;
     long long bi = 0;
-    if (lane == 0) bi = settle_equal_keys<L>(pc, n, c, j0, km, first);
+    if (lane == 0) bi = settle_equal_keys<L>(pc, n, c, j0, kmax, first);
     return __shfl(bi, 0);
 }
 
@@ -366,14 +375,24 @@ k_lu_eliminate(Bases bs, MatRef a, int64_t n, int64_t c, int64_t j0, int64_t je,
         }
     }
     if (keep) {
-        // the largest key of the workgroup's rows (0 for rows past n)
+        // the group record: the largest key of the workgroup's rows (0 for
+        // rows past n), the first row holding it, and whether another does
         if (tid == 0) skey[w] = key;
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long m = 0;
 #pragma unroll
             for (int k = 0; k < ELIM_ROWS; k++) m = skey[k] > m ? skey[k] : m;
-            pc.cmax_out[blockIdx.x] = m;
+            int kf = -1, nh = 0;
+#pragma unroll
+            for (int k = 0; k < ELIM_ROWS; k++)
+                if (skey[k] == m) {
+                    kf = kf < 0 ? k : kf;
+                    nh++;
+                }
+            pc.cmax_out[2 * blockIdx.x] = m;
+            pc.cmax_out[2 * blockIdx.x + 1] =
+                (unsigned long long)(c + 1 + (int64_t)blockIdx.x * ELIM_ROWS + kf) | (nh > 1 ? (1ull << 63) : 0ull);
         }
     }
 }

@@ -93,6 +93,32 @@ def test_lu_pivot_inside_panel_equal_keys_and_ties():
     assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
 
 
+def test_lu_pivot_equal_keys_inside_one_row_group():
+    """The column steps work on groups of four rows and record, per group, the
+    largest key, its first row and whether another row holds it.  Rows 5, 6
+    and 7 of column 1 hold 3/4, -(3/4 + 2^-200) and 3/4 + 2^-200: one key,
+    one group (rows 5..8 for column 1), and the first index of the largest
+    magnitude is row 6."""
+    p, n = 256, 40
+    A = I.uniform_pm1(n, n, p, 37)
+    zero, one = mpnum.from_int(0, p), mpnum.from_int(1, p)
+    I.set_entry(A, 0, 0, one, p)
+    for i in range(1, n):
+        I.set_entry(A, i, 0, zero, p)
+        half = mpnum.to_fraction(I.entry(A, i, 1, p), p) / 2
+        I.set_entry(A, i, 1, mpnum.from_fraction(half, p), p)
+    x = Fraction(3, 4)
+    y = x + Fraction(1, 1 << 200)
+    for i, v in ((5, x), (6, -y), (7, y)):
+        I.set_entry(A, i, 1, mpnum.from_fraction(v, p), p)
+    Fc, pc, ic = cref.lu(A, p, panel=8, algo="winograd", cutoff=2)
+    assert pc[1] == 6
+    Fg, pg, ig = gpu_lu(A, p, 8, mp.WINOGRAD, 2)
+    assert ig == ic == 0
+    assert list(pg) == list(pc)
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+
+
 def test_lu_many_rows_per_pivot_step():
     """n = 600 at 128 bits, panel 64: the pivot steps inside a panel read more
     than 512 rows' keys (several chunks per searching lane)."""
