@@ -75,7 +75,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G)
 // ------------------------------------------------------------------ Simple
 
 template <int L, int TM>
-__global__ void __launch_bounds__(64 * TM)
+__global__ void __launch_bounds__(64 * TM) __attribute__((amdgpu_waves_per_eu(leaf_waves(L))))
 k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
 {
     for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
@@ -163,7 +163,7 @@ __device__ __forceinline__ uint32_t lds_addr32(const uint32_t* p)
 // Every element keeps Simple's order (k ascending from exact zero), so Block
 // is bit-identical to Simple.
 template <int L, int TM, int TK>
-__global__ void __launch_bounds__(64 * TM)
+__global__ void __launch_bounds__(64 * TM) __attribute__((amdgpu_waves_per_eu(leaf_waves(L))))
 k_gemm_block(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ tile_task, int64_t ntiles, Bases bs)
 {
     constexpr int W = L + 2;                  // words (planes) per element

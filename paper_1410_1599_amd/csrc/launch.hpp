@@ -14,6 +14,15 @@ constexpr int GEMM_TM = 4;          // rows (waves) per workgroup of a leaf prod
 // 39 KB at 512, 74 KB at 1024
 constexpr int block_tk(int L) { return (void)L, 4; }
 
+// waves per SIMD the leaf kernels are compiled for (the register budget is
+// 512 / waves per lane; the compiler spills the rest to scratch): one wave's
+// memory and dependency waits need others to cover them.  Measured on the
+// MI355X: at 1024 bits 2 instead of 1 (280 registers) took the 1024^3
+// Simple product from 88.6 to 49.9 ms and Winograd from 53.3 to 31.7 ms; at
+// 512 bits 4 instead of 3, 4 % less; at 256 bits 6 instead of 5, 2 % less
+// (7 no better).  Same code, same bits.
+constexpr int leaf_waves(int L) { return L >= 32 ? 2 : (L == 16 ? 4 : (L == 8 ? 6 : 1)); }
+
 enum LeafKind { LEAF_SIMPLE = 0, LEAF_BLOCK = 1 };
 
 // grouped leaf products; tile_task[t] is the index (into tasks) of tile t's task
