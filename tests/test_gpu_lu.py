@@ -93,13 +93,15 @@ def test_lu_pivot_inside_panel_equal_keys_and_ties():
     assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
 
 
-def test_lu_pivot_equal_keys_inside_one_row_group():
+@pytest.mark.parametrize("p", [256, 1024])
+def test_lu_pivot_equal_keys_inside_one_row_group(p):
     """The column steps work on groups of four rows and record, per group, the
     largest key, its first row and whether another row holds it.  Rows 5, 6
     and 7 of column 1 hold 3/4, -(3/4 + 2^-200) and 3/4 + 2^-200: one key,
     one group (rows 5..8 for column 1), and the first index of the largest
-    magnitude is row 6."""
-    p, n = 256, 40
+    magnitude is row 6.  At 1024 bits the search from the copy runs as a
+    launch of its own."""
+    n = 40
     A = I.uniform_pm1(n, n, p, 37)
     zero, one = mpnum.from_int(0, p), mpnum.from_int(1, p)
     I.set_entry(A, 0, 0, one, p)
@@ -115,6 +117,19 @@ def test_lu_pivot_equal_keys_inside_one_row_group():
     assert pc[1] == 6
     Fg, pg, ig = gpu_lu(A, p, 8, mp.WINOGRAD, 2)
     assert ig == ic == 0
+    assert list(pg) == list(pc)
+    assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
+
+
+@pytest.mark.parametrize("n,panel", [(1, 1), (2, 1), (2, 2), (3, 2), (5, 4), (7, 3), (9, 8)])
+def test_lu_tiny_sizes(n, panel):
+    """Sizes below one four-row group, panels of one column, and a last
+    column whose step has no row below it."""
+    p = 256
+    A = I.uniform_pm1(n, n, p, 41 + n)
+    Fc, pc, ic = cref.lu(A, p, panel=panel, algo="winograd", cutoff=1)
+    Fg, pg, ig = gpu_lu(A, p, panel, mp.WINOGRAD, 1)
+    assert ig == ic
     assert list(pg) == list(pc)
     assert planes_equal(Fg, Fc), first_mismatch(Fg, Fc, p)
 
