@@ -656,6 +656,21 @@ k_lu_solve_reg(Bases bs, MatRef luT, MatRef x, const int32_t* piv, int64_t n)
             fc[k] = fn[k];
         }
     }
+    // up to 512 bits, and up to 32 limbs of rows per thread (beyond that the
+    // registers spill), each thread first forms the reciprocals of its rows'
+    // diagonal entries (recip_ext, all rows at once), so that the division on
+    // each backward step's critical path becomes a product and a rounding
+    // check (div_by_recip: the same bits as div_rn)
+    constexpr bool RECIP = L <= 16 && L * RPT <= 32;
+    MP<L + 2> rinv[RECIP ? RPT : 1];
+    if constexpr (RECIP) {
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+            const int r = tid + k * SOLVE_REG_THREADS;
+            const MP<L> d = r < n ? ldm<L>(bs, luT, r, r) : mp_zero<L>();
+            rinv[k] = is_zero<L>(d) ? mp_zero<L + 2>() : recip_ext<L>(d);
+        }
+    }
     // column n - 1 of U (its diagonal entry for the owner of row n - 1)
 #pragma unroll
     for (int k = 0; k < RPT; k++) {
@@ -667,7 +682,8 @@ k_lu_solve_reg(Bases bs, MatRef luT, MatRef x, const int32_t* piv, int64_t n)
 #pragma unroll
             for (int k = 0; k < RPT; k++)
                 if (k == t / SOLVE_REG_THREADS) {
-                    v[k] = div_rn<L>(v[k], fc[k]);
+                    if constexpr (RECIP) v[k] = div_by_recip<L>(v[k], fc[k], rinv[k]);
+                    else v[k] = div_rn<L>(v[k], fc[k]);
                     publish(t, v[k]);
                 }
         }
