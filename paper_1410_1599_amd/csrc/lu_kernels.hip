@@ -5,6 +5,7 @@
 #include "lanediv.hpp"
 #include "launch.hpp"
 #include "mp_arith.hpp"
+#include "recipdiv.hpp"
 
 namespace mpg {
 
