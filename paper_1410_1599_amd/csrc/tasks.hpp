@@ -20,9 +20,24 @@ struct Bases {
     uint32_t* const* ext;
 };
 
+// In a kernel the id is the same for the whole wave: the inline pointers are
+// chosen by selects (an indexed kernel-argument array would be read with a
+// vector load), and the table, which no kernel writes, is read through the
+// constant address space, so the pointer lands in scalar registers.
 __host__ __device__ inline uint32_t* base_ptr(const Bases& b, int32_t id)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if (id < NBASES) {
+        uint32_t* r = b.p[0];
+#pragma unroll
+        for (int q = 1; q < NBASES; q++) r = id == q ? b.p[q] : r;
+        return r;
+    }
+    typedef uint32_t* const __attribute__((address_space(4))) kptr;
+    return ((const kptr*)b.ext)[id - NBASES];
+#else
     return id < NBASES ? b.p[id] : b.ext[id - NBASES];
+#endif
 }
 
 // element (i, j), limb k of a matrix view: p[base][off + k * ps + i * ld + j];
