@@ -88,8 +88,10 @@ k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ ti
         const int64_t i = (lt / tn) * tr + (threadIdx.x >> T.tcl);
         const int64_t j = (lt % tn) * tc + (threadIdx.x & (tc - 1));
         if (i >= T.m || j >= T.n) continue;
-        uint32_t* C = wave_uniform(base_ptr(bs, T.C.base)) + T.C.off + i * T.C.ld + j;
-        MP<L> c = T.accum ? load<L>(C, T.C.ps, 0) : mp_zero<L>();
+        // C's address is formed where it is used (before and after the loop),
+        // so that no register holds it across the loop
+        MP<L> c = T.accum ? load<L>(wave_uniform(base_ptr(bs, T.C.base)) + T.C.off + i * T.C.ld + j, T.C.ps, 0)
+                          : mp_zero<L>();
         // a_ik at A + i * ia + k * ka: row-major, or a transposed copy (T.at)
         const int64_t ia = T.at ? 1 : T.A.ld, ka = T.at ? T.A.ld : 1;
         if (T.A.ps < (1 << 30) && T.B.ps < (1 << 30)) {
@@ -116,7 +118,7 @@ k_gemm_simple(const GemmTask* __restrict__ tasks, const int32_t* __restrict__ ti
                 c = add_rn<L>(c, mul_rn<L>(a, b));
             }
         }
-        store<L>(C, T.C.ps, 0, c);
+        store<L>(wave_uniform(base_ptr(bs, T.C.base)) + T.C.off + i * T.C.ld + j, T.C.ps, 0, c);
     }
 }
 
