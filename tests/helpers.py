@@ -90,3 +90,49 @@ def first_mismatch(X, Y, p):
         return None
     i, j = (int(v) for v in pos[0])
     return (i, j, I.entry(X, i, j, p), I.entry(Y, i, j, p), int(diff.sum()))
+
+
+def division_stress_matrix(p, n, K, seed):
+    """First K columns lower triangular: a_jj is a divisor built to strain the
+    radix-2^32 digit estimate, the entries below it are dividends of smaller
+    magnitude, the entries above it zero (so no earlier step changes column j
+    and its pivot is row j).  Columns from K on are uniform in [-1, 1)."""
+    rng = random.Random(seed)
+    A = I.uniform_pm1(n, n, p, seed)
+    one, full = 1 << (p - 1), (1 << p) - 1
+    zero = (0, 0)
+    top_equal = 0
+    for j in range(K):
+        run = rng.randrange(1, p - 64)
+        kind = j % 3
+        if kind == 0:                    # 1 0...0 1...1: top limbs 2^31, 0
+            my = one | ((1 << run) - 1)
+        elif kind == 1:                  # 1...1 0...0
+            my = full ^ ((1 << run) - 1)
+        else:
+            my = rng.randrange(one + 1, 1 << p)
+        ey = rng.randrange(-3, 4)
+        I.set_entry(A, j, j, (my if rng.random() < 0.5 else -my, ey), p)
+        for i in range(j):
+            I.set_entry(A, i, j, zero, p)
+        for i in range(j + 1, n):
+            pick = (i + j) % 5
+            if pick == 0:                # just below the divisor: the same top limbs
+                mx, ex = max(one, my - rng.randrange(1, 1 << 16)), ey
+            elif pick == 1:              # 1 0...0 over a divisor with ones below its top bit
+                mx, ex = one, ey
+            elif pick == 2:
+                mx, ex = rng.randrange(one, 1 << p), ey - 1
+            elif pick == 3:              # the divisor's top 64 bits over smaller low bits
+                low = my & ((1 << (p - 64)) - 1)
+                mx, ex = (my ^ low) | rng.randrange(0, low + 1), ey
+                mx = mx if mx < my else my - 1
+            else:
+                mx, ex = 0, 0
+            if mx == 0:
+                I.set_entry(A, i, j, zero, p)
+                continue
+            assert one <= mx < (1 << p) and (ex < ey or mx < my)     # |a_ij| < |a_jj|
+            top_equal += (mx >> (p - 64)) == (my >> (p - 64))
+            I.set_entry(A, i, j, (mx if rng.random() < 0.5 else -mx, ex), p)
+    return A, top_equal

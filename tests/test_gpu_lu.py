@@ -10,7 +10,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from helpers import first_mismatch, planes_equal
+from helpers import division_stress_matrix, first_mismatch, planes_equal
 from oracle import cref, lu as LU, mpnum
 from paper_1410_1599_amd import inputs as I
 
@@ -268,53 +268,6 @@ def test_bench_residual_matches_oracle(kind):
     assert l2_ref < -p + 20
 
 
-def _division_stress_matrix(p, n, K, seed):
-    """First K columns lower triangular: a_jj is a divisor built to strain the
-    radix-2^32 digit estimate, the entries below it are dividends of smaller
-    magnitude, the entries above it zero (so no earlier step changes column j
-    and its pivot is row j).  Columns from K on are uniform in [-1, 1)."""
-    import random
-    rng = random.Random(seed)
-    A = I.uniform_pm1(n, n, p, seed)
-    one, full = 1 << (p - 1), (1 << p) - 1
-    zero = mpnum.from_int(0, p)
-    top_equal = 0
-    for j in range(K):
-        run = rng.randrange(1, p - 64)
-        kind = j % 3
-        if kind == 0:                    # 1 0...0 1...1: top limbs 2^31, 0
-            my = one | ((1 << run) - 1)
-        elif kind == 1:                  # 1...1 0...0
-            my = full ^ ((1 << run) - 1)
-        else:
-            my = rng.randrange(one + 1, 1 << p)
-        ey = rng.randrange(-3, 4)
-        I.set_entry(A, j, j, (my if rng.random() < 0.5 else -my, ey), p)
-        for i in range(j):
-            I.set_entry(A, i, j, zero, p)
-        for i in range(j + 1, n):
-            pick = (i + j) % 5
-            if pick == 0:                # just below the divisor: the same top limbs
-                mx, ex = max(one, my - rng.randrange(1, 1 << 16)), ey
-            elif pick == 1:              # 1 0...0 over a divisor with ones below its top bit
-                mx, ex = one, ey
-            elif pick == 2:
-                mx, ex = rng.randrange(one, 1 << p), ey - 1
-            elif pick == 3:              # the divisor's top 64 bits over smaller low bits
-                low = my & ((1 << (p - 64)) - 1)
-                mx, ex = (my ^ low) | rng.randrange(0, low + 1), ey
-                mx = mx if mx < my else my - 1
-            else:
-                mx, ex = 0, 0
-            if mx == 0:
-                I.set_entry(A, i, j, zero, p)
-                continue
-            assert one <= mx < (1 << p) and (ex < ey or mx < my)     # |a_ij| < |a_jj|
-            top_equal += (mx >> (p - 64)) == (my >> (p - 64))
-            I.set_entry(A, i, j, (mx if rng.random() < 0.5 else -mx, ex), p)
-    return A, top_equal
-
-
 @pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_lu_multipliers_strain_the_digit_estimate(p):
     """The multipliers l_ij = a_ij / a_jj are divided by a whole wave, limb per
@@ -325,7 +278,7 @@ def test_lu_multipliers_strain_the_digit_estimate(p):
     The columns are the first column of a panel (its own launch) and the columns
     after it (the fused step).  Factors and pivots must equal the oracle's."""
     n, K = 70, 64
-    A, top_equal = _division_stress_matrix(p, n, K, 77 + p)
+    A, top_equal = division_stress_matrix(p, n, K, 77 + p)
     assert top_equal > 300
     # Simple trailing updates: the zeros above the diagonal then subtract exact
     # zeros from the later crafted columns (Winograd's quadrant sums would mix

@@ -218,3 +218,26 @@ def test_unpivoted_lotkin_solve_close_to_arange():
     xs = LU.solve(F, piv, b, p)
     err = max(abs(mpnum.to_fraction(v, p) - i) for i, v in enumerate(xs))
     assert err < Fraction(1, 2 ** 200)
+
+
+@pytest.mark.parametrize("p", [128, 1024])
+def test_division_stress_matrix_pivots_and_multipliers(p):
+    """The matrix that strains the GPU's lane division (tests/helpers.py): in the
+    oracle's LU its first K pivots are the diagonal, and every multiplier
+    l_ij (j < K) is the correctly rounded quotient of the entries as built
+    (the zeros above the diagonal leave column j unchanged until its step);
+    exchanges of later columns move whole rows, multipliers included."""
+    from helpers import division_stress_matrix
+    n, K = 70, 64
+    A, top_equal = division_stress_matrix(p, n, K, 77 + p)
+    assert top_equal > 300
+    F, piv, info = cref.lu(A, p, panel=32, algo="simple", cutoff=8)
+    assert info == 0 and list(piv[:K]) == list(range(K))
+    row = list(range(n))
+    for c in range(n):
+        r = int(piv[c])
+        row[c], row[r] = row[r], row[c]
+    for j in range(K):
+        y = I.entry(A, j, j, p)
+        for i in range(j + 1, n):
+            assert I.entry(F, i, j, p) == mpnum.div(I.entry(A, row[i], j, p), y, p), (i, j)
